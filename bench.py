@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSOS deposition sweep on one MI355X.
+
+A step is one sweep (L^2 attempted depositions, both checkerboard phases and
+the fused exact sums) of the single 16384^2 surface, N = 1, D = 8, flat
+start, seed 1.  The timed region is K consecutive sweeps issued as one
+rsos_sweep call, bracketed by device synchronisation; the lattice is already
+resident in HBM when it starts.
+
+Printed JSON line (one): attempts per ns over the timed region, plus
+  roofline      the tile-block kernel's algorithmic HBM bytes (one read and
+                one write of each int32 site per sweep: 8 B per attempt)
+                divided by its mean duration, measured with HIP events on the
+                surface's stream over the timed region, against 8 TB/s;
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload
+                (a few sweeps of the same surface), all host cores;
+  batched       the ensemble of 256 surfaces (L in {256..2048}) in one launch
+                per sweep versus the same surfaces one surface per launch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_ATTEMPT = 8  # int32 read + write per site per sweep
+
+
+def _cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(L, N, D, seed, budget_s=12.0):
+    """The oracle as it stands, timed on the host on a few sweeps of the
+    same surface (bounded to ~budget_s of CPU work)."""
+    import numpy as np
+    from oracle import ref
+    import workloads
+    threads = min(_cores(), 16)
+    ref.build()
+    ref.set_threads(threads)
+    h = workloads.flat(L)
+    sweeps = 0
+    t0 = time.perf_counter()
+    while True:
+        ref.run(h, L, N, D, seed=seed, t0=sweeps, n=1, log=False)
+        sweeps += 1
+        if time.perf_counter() - t0 > budget_s or sweeps >= 64:
+            break
+    dt = time.perf_counter() - t0
+    ref.set_threads(0)
+    return {"value": round(sweeps * L * L / (dt * 1e9), 4), "unit": "attempted site updates/ns",
+            "cores": threads, "kind": "oracle",
+            "sample": f"first {sweeps} sweeps of the L={L} N={N} D={D} surface from flat, "
+                      f"{dt:.1f} s, OpenMP over the tiles of a phase"}
+
+
+def bench_batched(n_steps_batch=200):
+    """Aggregate attempts/ns: 256-surface ensemble, one launch per sweep for
+    all surfaces, versus one surface per launch (same surfaces, same sweeps)."""
+    import torch
+    import paper_1605_02620_amd as rsos
+    import workloads
+    ens = workloads.cfg_ensemble()
+    specs = [(s.L, s.N, s.seed) for s in ens]
+    total_sites = sum(L * L for (L, _, _) in specs)
+    b = rsos.Batch(specs, D=8, log_cap=4096, stream=torch.cuda.Stream())
+    b.sweep(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(n_steps_batch)
+    b.width()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    # plain: every surface its own handle, sweeps issued surface by surface
+    st = torch.cuda.Stream()
+    surfs = [rsos.Surface(L, N=N, seed=sd, D=8, log_cap=4096, stream=st) for (L, N, sd) in specs]
+    for s in surfs:
+        s.sweep(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in surfs:
+        s.sweep(n_steps_batch)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    for s in surfs:
+        s.close()
+    rate_b = total_sites * n_steps_batch / (tb * 1e9)
+    rate_p = total_sites * n_steps_batch / (tp * 1e9)
+    return {"workload": "256 surfaces, L from {256,512,1024,2048} (default_rng(20160508)), "
+                        f"N=1, D=8, seeds 0..255, {n_steps_batch} sweeps each",
+            "batched_attempts_per_ns": round(rate_b, 2), "plain_attempts_per_ns": round(rate_p, 2),
+            "batched_over_plain": round(rate_b / rate_p, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(independent surfaces shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1605_02620_amd as rsos
+    import workloads
+
+    cfg = workloads.cfg_single()
+    L, N, D, seed = cfg.L, cfg.N, cfg.D, cfg.seed
+    stream = torch.cuda.Stream()
+    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=max(4096, args.steps + args.warmup + 1),
+                     stream=stream)
+    s.sweep(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: K sweeps, hipGraph replays of the two kernels per sweep
+    t0 = time.perf_counter()
+    s.sweep(args.steps)
+    s.width()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    attempts = L * L * args.steps
+    value = attempts / (dt * 1e9)
+
+    # same region again with every tile-block kernel bracketed by HIP events
+    # on the surface's stream (graph replay off): the dominant kernel's
+    # mean duration
+    s.timing(True)
+    torch.cuda.synchronize()
+    k_steps = min(args.steps, 400)
+    s.sweep(k_steps)
+    launches, mean_ms, _ = s.timing_read()
+    s.timing(False)
+    w = s.width()
+    s.close()
+    achieved = L * L * BYTES_PER_ATTEMPT / (mean_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "block_sweep<8,16,8,64>", "launches_timed": launches,
+                "kernel_mean_ms": round(mean_ms, 4),
+                "bytes_per_launch": L * L * BYTES_PER_ATTEMPT}
+
+    out = {"metric": "attempted site updates/ns", "value": round(value, 3),
+           "unit": "attempts/ns", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+           "config": {"workload": f"single RSOS surface L={L} periodic, N={N}, D={D}, flat int32 "
+                                  f"start, seed {seed}, {args.steps} sweeps timed after "
+                                  f"{args.warmup} warm-up sweeps",
+                      "L": L, "N": N, "D": D, "seed": seed, "sweeps": args.steps,
+                      "final_t": int(w["t"]), "final_w2": float(w["w2"])},
+           "roofline": roofline}
+    if not args.no_batch:
+        out["batched"] = bench_batched()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(L, N, D, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

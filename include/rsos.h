@@ -1,0 +1,243 @@
+/*
+ * rsos.h -- C ABI of librsos.so, the gfx950 RSOS deposition sweep.
+ *
+ * The library simulates restricted solid-on-solid (RSOS) growth on an
+ * L x L periodic square lattice of int32 heights (Kelling, Odor & Gemming,
+ * "Universality of (2+1)-dimensional restricted solid-on-solid models"):
+ *
+ *   - deposition h_i -> h_i + 1 at a randomly chosen site is accepted only
+ *     if afterwards |h_i - h_j| <= N for all 4 nearest neighbours j
+ *     (the RSOS restriction, Sec. I);
+ *   - time is counted in Monte-Carlo steps, one sweep = L*L attempts,
+ *     starting from a flat surface (Sec. II);
+ *   - the attempts are scheduled by a domain decomposition into D x D tiles
+ *     whose origin moves randomly after each sweep (Sec. II): tiles are
+ *     coloured like a checkerboard, colour 0 is updated, then colour 1, and
+ *     each tile makes D*D sequential uniform attempts inside itself;
+ *   - after every sweep the library records S1 = sum h, S2 = sum h^2 and
+ *     the accepted count A (exact int64), from which the squared width
+ *     W^2(L, t) of Eq. (2) follows.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed
+ * (key = (seed mod 2^32, seed >> 32)); sweep s (0-based) draws its origin
+ * from counter (0, 0, s, 2), ox = r0 mod 2D, oy = r1 mod 2D; tile tile_id =
+ * ty*(L/D) + tx of the shifted frame in phase p draws its D*D in-tile sites
+ * from counters (j, tile_id, s, p), j = 0, 1, ..., splitting each output
+ * word into floor(32/b) fields of b = 2 log2(D) bits, lowest field first;
+ * field r is the site (r mod D, r / D) of the tile.  A trajectory is a
+ * function of (L, N, D, seed, initial heights, t0, number of sweeps) only:
+ * never of launch shapes, batching, streams or timing.
+ *
+ * Memory: heights are int32, row-major (index y*L + x), in device memory
+ * owned by the caller.  Each surface needs two such buffers (the sweep reads
+ * one and writes the other); after t sweeps the current state is in the
+ * buffer of parity t (bufs[t & 1] with bufs = {d_h, d_work}).  The library
+ * owns only small device buffers of its own (per-sweep log, partial sums).
+ *
+ * Errors: every function returns an rsos_status; nothing aborts and no C++
+ * exception crosses this boundary.  rsos_last_error() gives a thread-local
+ * message for the last failure.  After a HIP runtime error a handle is
+ * failed for good and later calls return RSOS_E_STATE.  Handles are not
+ * thread-safe; distinct handles on distinct streams are independent.
+ */
+#ifndef RSOS_H
+#define RSOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSOS_OK = 0,
+    RSOS_E_INVAL = -1,    /* invalid argument (size, pointer, range)          */
+    RSOS_E_RSOS = -2,     /* initial heights violate |h_i - h_j| <= N          */
+    RSOS_E_OVERFLOW = -3, /* heights or sum h^2 could leave int32 / int64     */
+    RSOS_E_DEVICE = -4,   /* HIP runtime error (handle becomes failed)        */
+    RSOS_E_NOMEM = -5,    /* library-owned device or host allocation failed   */
+    RSOS_E_STATE = -6,    /* handle failed earlier, or call out of sequence   */
+    RSOS_E_BUSY = -7      /* serving engine: no room for this job right now   */
+} rsos_status;
+
+/* Parameters of one surface.
+ *   L    lattice side, a multiple of 2*D, 2*D <= L <= 65536;
+ *   N    step restriction of Sec. I, N >= 1 (INT32_MAX: no restriction);
+ *   D    tile side of the domain decomposition, one of 2, 4, 8, 16
+ *        (the paper uses 8 x 8 domains, Sec. II, and tests 16 x 16,
+ *        Sec. III.C); part of the result;
+ *   seed 64-bit Philox key. */
+typedef struct {
+    int32_t L;
+    int32_t N;
+    int32_t D;
+    int32_t reserved; /* must be 0 */
+    uint64_t seed;
+} rsos_params;
+
+/* One record of the per-sweep log: the state after t sweeps.
+ *   s1 = sum h, s2 = sum h^2 (exact), accepted = accepted attempts of sweep
+ *   t (0 for the initial state), w2 = W^2(L, t) of Eq. (2) evaluated as
+ *   (L^2 s2 - s1^2) / L^4 from the exact int128 numerator (one rounding to
+ *   double when L is a power of two). */
+typedef struct {
+    int64_t t;
+    int64_t s1;
+    int64_t s2;
+    int64_t accepted;
+    double w2;
+} rsos_width_t;
+
+typedef struct rsos_surface rsos_surface;
+typedef struct rsos_batch rsos_batch;
+typedef struct rsos_engine rsos_engine;
+
+/* --------------------------------------------------------------------- */
+/* Single surface (the plain one-surface path).                            */
+/* --------------------------------------------------------------------- */
+
+/* Creates a surface handle.
+ *   out       receives the handle;
+ *   p         parameters (validated here: RSOS_E_INVAL);
+ *   d_h       caller-owned device int32[L*L]; must outlive the handle;
+ *   d_work    caller-owned device int32[L*L], the second buffer; NULL makes
+ *             the library allocate (and later free) its own;
+ *   h0_host   host int32[L*L] initial heights, 0 <= h < 2^30, checked for
+ *             the restriction (RSOS_E_RSOS); NULL means flat h = 0 (Sec. II);
+ *   t0        sweeps already done (resume from a checkpoint), 0 <= t0 < 2^32;
+ *   log_cap   sweeps kept in the device log ring (0 = 65536);
+ *   stream    hipStream_t the surface works on (NULL = default stream).
+ * The initial state is copied into the buffer of parity t0. */
+rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, int32_t *d_work,
+                      const int32_t *h0_host, int64_t t0, int64_t log_cap, void *stream);
+
+/* Enqueues n_mcs sweeps (asynchronous on the surface's stream); t += n_mcs.
+ * Checks the overflow bound max(h0) + min(t + N L, D^2 t) < 2^31 and
+ * L^2 H^2 < 2^63 before enqueuing (RSOS_E_OVERFLOW). */
+rsos_status rsos_sweep(rsos_surface *s, int64_t n_mcs);
+
+/* Synchronises the stream and returns the record of the current time t. */
+rsos_status rsos_width(rsos_surface *s, rsos_width_t *out);
+
+/* Synchronises and returns records t_from .. t_from+n-1 (t_from >= t0).
+ * Records older than log_cap sweeps before the current time are gone
+ * (RSOS_E_INVAL). */
+rsos_status rsos_log(rsos_surface *s, int64_t t_from, int64_t n, rsos_width_t *out);
+
+/* Synchronises and copies the current heights (int32[L*L]) to dst, host or
+ * device memory as dst_is_device says. */
+rsos_status rsos_heights(rsos_surface *s, int32_t *dst, int dst_is_device);
+
+/* Current time t and the device buffer that holds the current state. */
+rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current);
+
+/* Kernel timing.  While enabled, every tile-block sweep kernel launch of
+ * the surface is bracketed by HIP events on the surface's stream (sweeps
+ * are then issued one by one, not as hipGraph replays).  rsos_timing_read
+ * synchronises and returns the number of timed launches and their mean and
+ * total duration in milliseconds; it also clears the record. */
+rsos_status rsos_timing(rsos_surface *s, int enable);
+rsos_status rsos_timing_read(rsos_surface *s, int64_t *launches, double *mean_ms, double *total_ms);
+
+/* Frees the handle and library-owned memory (never d_h, never a
+ * caller-provided d_work).  Synchronises the stream first. */
+rsos_status rsos_free(rsos_surface *s);
+
+/* --------------------------------------------------------------------- */
+/* Batched ensemble: many independent surfaces (any L, N, seed; one D) in   */
+/* one launch per sweep.  Independent realization sets, Sec. II.          */
+/* --------------------------------------------------------------------- */
+
+/* n surfaces; p[i] their parameters (all with the same D);
+ * d_pool / d_work_pool caller-owned device int32 pools, surface i at
+ * element offsets[i] of each (L_i^2 elements, offsets[] host array);
+ * d_work_pool NULL makes the library allocate the second pool.  Flat start,
+ * t = 0 for all. */
+rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, int32_t *d_pool,
+                            int32_t *d_work_pool, const int64_t *offsets, int64_t log_cap,
+                            void *stream);
+
+/* Enqueues sweeps: surface i advances n_mcs[i] sweeps (n_mcs NULL: every
+ * surface advances n_all).  Surfaces that are done idle in later launches. */
+rsos_status rsos_batch_sweep(rsos_batch *b, const int64_t *n_mcs, int64_t n_all);
+
+/* Synchronises; out[i] = record of surface i at its current time. */
+rsos_status rsos_batch_width(rsos_batch *b, rsos_width_t *out);
+
+/* Synchronises; per-sweep records of surface i, as rsos_log. */
+rsos_status rsos_batch_log(rsos_batch *b, int32_t i, int64_t t_from, int64_t n, rsos_width_t *out);
+
+/* Synchronises; copies surface i's current heights. */
+rsos_status rsos_batch_heights(rsos_batch *b, int32_t i, int32_t *dst, int dst_is_device);
+
+rsos_status rsos_batch_free(rsos_batch *b);
+
+/* --------------------------------------------------------------------- */
+/* Serving engine: continuous batching of simulation jobs.                 */
+/* --------------------------------------------------------------------- */
+
+/* Job states reported by rsos_engine_poll. */
+enum { RSOS_JOB_QUEUED = 0, RSOS_JOB_RUNNING = 1, RSOS_JOB_DONE = 2, RSOS_JOB_CANCELLED = 3 };
+
+/* Creates an engine over a caller-owned device pool of pool_bytes bytes.
+ * Jobs are admitted in arrival order while their footprint (2 L^2 int32
+ * buffers, 256-byte aligned) fits in the free pool and fewer than
+ * max_running jobs run.  Every running job advances one sweep per tick; a
+ * tick is one launch over all running jobs. */
+rsos_status rsos_engine_create(rsos_engine **out, void *d_pool, int64_t pool_bytes,
+                               int32_t max_running, int32_t D, void *stream);
+
+/* Queues a job: parameters p (p->D must equal the engine's D), t_max
+ * sweeps, and the sweep times (1 <= t <= t_max, increasing) at which its
+ * width record is kept.  *job_id receives the id.  RSOS_E_INVAL if the job
+ * could never fit the pool. */
+rsos_status rsos_engine_submit(rsos_engine *e, const rsos_params *p, int64_t t_max,
+                               const int64_t *sample_t, int32_t n_samples, int64_t *job_id);
+
+/* Admits what fits, then runs up to max_ticks ticks (stopping early when
+ * nothing runs), retiring finished jobs and admitting queued ones between
+ * ticks.  *n_finished (may be NULL) receives the jobs that finished. */
+rsos_status rsos_engine_step(rsos_engine *e, int64_t max_ticks, int32_t *n_finished);
+
+/* State of a job (RSOS_JOB_*) and its current sweep count. */
+rsos_status rsos_engine_poll(rsos_engine *e, int64_t job_id, int32_t *state, int64_t *t);
+
+/* Results of a finished job: its n_samples width records (at the requested
+ * times) and, if heights_host is non-NULL, its final int32[L*L] heights.
+ * A job's results stay until rsos_engine_release. */
+rsos_status rsos_engine_result(rsos_engine *e, int64_t job_id, rsos_width_t *samples,
+                               int32_t *heights_host);
+
+/* Drops a queued or running job (its memory is freed at the next tick). */
+rsos_status rsos_engine_cancel(rsos_engine *e, int64_t job_id);
+
+/* Forgets a finished or cancelled job's stored results. */
+rsos_status rsos_engine_release(rsos_engine *e, int64_t job_id);
+
+/* Counters: [0] queued, [1] running, [2] finished, [3] bytes in use,
+ * [4] ticks, [5] attempted site updates so far. */
+rsos_status rsos_engine_stats(rsos_engine *e, int64_t out[6]);
+
+rsos_status rsos_engine_destroy(rsos_engine *e);
+
+/* --------------------------------------------------------------------- */
+/* Utilities.                                                             */
+/* --------------------------------------------------------------------- */
+
+/* The library's own Philox4x32-10 block function, run on the host: out =
+ * f_key(ctr).  The device kernels use the same code. */
+void rsos_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* W^2 of Eq. (2) from the exact sums, as stored in rsos_width_t.w2. */
+double rsos_w2(int32_t L, int64_t s1, int64_t s2);
+
+const char *rsos_strerror(rsos_status st);
+const char *rsos_last_error(void);
+
+/* Library version string. */
+const char *rsos_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,780 @@
+// rsos.hip -- host runtime and C ABI of librsos.so (see include/rsos.h).
+//
+// Launch plan per sweep: block_sweep over every tile block of every active
+// surface, then reduce_partials (one workgroup per surface).  Both kernels
+// read the surface time t from device memory, so a captured hipGraph of K
+// sweeps replays for any t.  Surfaces whose L^2 int32 fit in LDS run all
+// their sweeps in one lds_run launch instead.
+#include "rsos.h"
+#include "rsos_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+using rsosk::SurfDev;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rsos_status fail(rsos_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(RSOS_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kLdsMaxBytes = 64 * 1024;  // lds_run: whole surface in LDS
+constexpr int kReduceNT = 256;
+constexpr int kGraphSweeps = 32;
+
+// ---------------------------------------------------------------------------
+// Block-kernel variants.  The tile block shape never changes results; it
+// only has to tile the lattice: T % TX == 0, T % TY == 0, region <= L.
+// ---------------------------------------------------------------------------
+typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int, long long *);
+
+template <int D, int TX, int TY, int NT>
+void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, long long *p)
+{
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT>), grid, dim3(NT), 0, st, d, n, p);
+}
+
+struct Variant {
+    int D, TX, TY, NT;
+    BlockLaunch launch;
+};
+
+const Variant kVariants[] = {
+    {2, 32, 32, 256, launch_block<2, 32, 32, 256>},
+    {2, 2, 2, 64, launch_block<2, 2, 2, 64>},
+    {4, 16, 16, 128, launch_block<4, 16, 16, 128>},
+    {4, 2, 2, 64, launch_block<4, 2, 2, 64>},
+    {8, 16, 8, 64, launch_block<8, 16, 8, 64>},
+    {8, 8, 8, 64, launch_block<8, 8, 8, 64>},
+    {8, 2, 2, 64, launch_block<8, 2, 2, 64>},
+    {16, 4, 4, 64, launch_block<16, 4, 4, 64>},
+    {16, 2, 2, 64, launch_block<16, 2, 2, 64>},
+};
+
+bool variant_fits(const Variant &v, int L)
+{
+    const int T = L / v.D;
+    const int rw = v.TX * v.D + 2 * (v.D + 1), rh = v.TY * v.D + 2 * (v.D + 1);
+    return T % v.TX == 0 && T % v.TY == 0 && rw <= L && rh <= L;
+}
+
+// First fitting variant for D that fits every L in Ls (optionally forced
+// by the RSOS_VARIANT environment variable "TXxTY").
+const Variant *pick_variant(int D, const std::vector<int> &Ls)
+{
+    const char *force = getenv("RSOS_VARIANT");
+    for (const Variant &v : kVariants) {
+        if (v.D != D) continue;
+        if (force) {
+            char want[32];
+            snprintf(want, sizeof want, "%dx%d", v.TX, v.TY);
+            if (strcmp(force, want) != 0) continue;
+        }
+        bool ok = true;
+        for (int L : Ls) ok = ok && variant_fits(v, L);
+        if (ok) return &v;
+    }
+    return nullptr;
+}
+
+typedef void (*LdsLaunch)(dim3, size_t, hipStream_t, SurfDev *, const int *);
+template <int D>
+void launch_lds(dim3 grid, size_t shm, hipStream_t st, SurfDev *d, const int *w)
+{
+    hipLaunchKernelGGL((rsosk::lds_run<D, 256>), grid, dim3(256), shm, st, d, w);
+}
+LdsLaunch lds_launcher(int D)
+{
+    switch (D) {
+    case 2: return launch_lds<2>;
+    case 4: return launch_lds<4>;
+    case 8: return launch_lds<8>;
+    case 16: return launch_lds<16>;
+    }
+    return nullptr;
+}
+
+bool valid_D(int D) { return D == 2 || D == 4 || D == 8 || D == 16; }
+
+rsos_status check_params(const rsos_params *p)
+{
+    if (!p) return fail(RSOS_E_INVAL, "params is NULL");
+    if (!valid_D(p->D)) return fail(RSOS_E_INVAL, "D=%d: must be 2, 4, 8 or 16", p->D);
+    if (p->L < 2 * p->D || p->L > 65536 || p->L % (2 * p->D) != 0)
+        return fail(RSOS_E_INVAL, "L=%d: must be a multiple of 2D=%d in [2D, 65536]", p->L, 2 * p->D);
+    if (p->N < 1) return fail(RSOS_E_INVAL, "N=%d: must be >= 1", p->N);
+    if (p->reserved != 0) return fail(RSOS_E_INVAL, "reserved field must be 0");
+    return RSOS_OK;
+}
+
+bool uses_lds(int L) { return (long long)L * L * 4 <= kLdsMaxBytes; }
+
+// H bounds every height after dt more sweeps: the mean grows at most one
+// per sweep and the restriction keeps the spread on the torus <= N L; also
+// no site gets more than D^2 deposits per sweep.
+rsos_status check_overflow(const rsos_params &p, long long max_h0, long long dt)
+{
+    const __int128 a = (__int128)dt + (__int128)p.N * p.L;
+    const __int128 b = (__int128)dt * p.D * p.D;
+    const __int128 H = (__int128)max_h0 + (a < b ? a : b);
+    if (H >= ((__int128)1 << 31) - 1) return fail(RSOS_E_OVERFLOW, "heights could reach 2^31");
+    const __int128 LH = (__int128)p.L * H;
+    if (LH * LH >= ((__int128)1 << 63)) return fail(RSOS_E_OVERFLOW, "sum h^2 could reach 2^63");
+    return RSOS_OK;
+}
+
+double w2_of(int L, long long s1, long long s2)
+{
+    const __int128 L2 = (__int128)L * L;
+    const __int128 num = L2 * s2 - (__int128)s1 * s1;
+    return (double)num / ((double)L2 * (double)L2);
+}
+
+rsos_status validate_h0(const int32_t *h, int L, int N, long long *max_h, long long *s1, long long *s2)
+{
+    long long mx = 0, a = 0, b = 0;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            const long long c = h[(size_t)y * L + x];
+            if (c < 0 || c >= (1ll << 30)) return fail(RSOS_E_INVAL, "h0 outside [0, 2^30)");
+            const long long r = h[(size_t)y * L + (x + 1) % L];
+            const long long u = h[(size_t)((y + 1) % L) * L + x];
+            if (llabs(c - r) > N || llabs(c - u) > N)
+                return fail(RSOS_E_RSOS, "h0 violates |dh| <= %d at (%d, %d)", N, x, y);
+            mx = std::max(mx, c);
+            a += c;
+            b += c * c;
+        }
+    *max_h = mx;
+    *s1 = a;
+    *s2 = b;
+    return RSOS_OK;
+}
+
+// Pinned staging for small host->device descriptor updates; the event makes
+// sure the previous copy is done before the buffer is rewritten.
+struct Staging {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+
+    rsos_status ensure(size_t n)
+    {
+        if (!done) HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        if (pending) {
+            HIP_TRY(hipEventSynchronize(done));
+            pending = false;
+        }
+        if (n > bytes) {
+            if (host) HIP_TRY(hipHostFree(host));
+            host = nullptr;
+            HIP_TRY(hipHostMalloc(&host, n, hipHostMallocDefault));
+            bytes = n;
+        }
+        return RSOS_OK;
+    }
+    rsos_status copy_to(void *dev, size_t n, hipStream_t st)
+    {
+        HIP_TRY(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipEventRecord(done, st));
+        pending = true;
+        return RSOS_OK;
+    }
+    void release()
+    {
+        if (pending && done) (void)hipEventSynchronize(done);
+        if (host) (void)hipHostFree(host);
+        if (done) (void)hipEventDestroy(done);
+        host = nullptr;
+        done = nullptr;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// A group of surfaces sharing one D: the common core of the single-surface,
+// batch and engine front ends.
+// ---------------------------------------------------------------------------
+struct SurfaceGroup {
+    int D = 8;
+    hipStream_t stream = nullptr;
+    bool failed = false;
+    std::vector<SurfDev> host;         // host mirror (t, t_end kept current)
+    std::vector<long long> max_h0, t0; // per surface
+    SurfDev *d_desc = nullptr;
+    long long *d_partials = nullptr;
+    std::vector<int> lds_idx, blk_idx; // surfaces on each path
+    int *d_lds_idx = nullptr;
+    const Variant *variant = nullptr;
+    int total_blocks = 0;
+    size_t lds_bytes = 0;
+    Staging staging;
+    hipGraphExec_t graph = nullptr;
+    int graph_sweeps = 0;
+    bool timing = false;                             // bracket block launches with events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+    std::vector<void *> owned;         // library-owned device allocations
+
+    rsos_status dev_alloc(void **p, size_t n)
+    {
+        hipError_t e = hipMalloc(p, n);
+        if (e != hipSuccess) return fail(RSOS_E_NOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
+        owned.push_back(*p);
+        return RSOS_OK;
+    }
+
+    // Builds the descriptor table (host side must be filled: buf, log, L, N,
+    // key, t, t_end).  Picks a block variant for the block-path surfaces.
+    rsos_status setup()
+    {
+        const int n = (int)host.size();
+        std::vector<int> Ls;
+        for (int i = 0; i < n; ++i) {
+            if (uses_lds(host[i].L)) lds_idx.push_back(i);
+            else { blk_idx.push_back(i); Ls.push_back(host[i].L); }
+        }
+        if (!blk_idx.empty()) {
+            variant = pick_variant(D, Ls);
+            if (!variant) return fail(RSOS_E_INVAL, "no tile-block shape fits these lattice sizes");
+        }
+        // block path surfaces first in the table, sorted by block_start
+        long long blocks = 0;
+        for (int i : blk_idx) {
+            SurfDev &s = host[i];
+            const int T = s.L / D;
+            s.nbx = T / variant->TX;
+            s.nblocks = s.nbx * (T / variant->TY);
+            s.block_start = (int)blocks;
+            s.part_start = blocks;
+            blocks += s.nblocks;
+            if (blocks > (1ll << 30)) return fail(RSOS_E_INVAL, "too many tile blocks");
+        }
+        total_blocks = (int)blocks;
+        for (int i : lds_idx) {
+            host[i].nbx = 0;
+            host[i].nblocks = 0;
+            host[i].block_start = 1 << 30;  // never matched by a block workgroup
+            host[i].part_start = 0;
+        }
+        rsos_status st;
+        if ((st = dev_alloc((void **)&d_desc, sizeof(SurfDev) * n)) != RSOS_OK) return st;
+        if (total_blocks > 0 &&
+            (st = dev_alloc((void **)&d_partials, sizeof(long long) * 3 * total_blocks)) != RSOS_OK)
+            return st;
+        if (!lds_idx.empty()) {
+            if ((st = dev_alloc((void **)&d_lds_idx, sizeof(int) * lds_idx.size())) != RSOS_OK) return st;
+            // device-table positions of the LDS-path surfaces (they follow
+            // the block-path ones)
+            std::vector<int> pos(lds_idx.size());
+            for (size_t k = 0; k < pos.size(); ++k) pos[k] = (int)(blk_idx.size() + k);
+            HIP_TRY(hipMemcpy(d_lds_idx, pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice));
+            int maxL = 0;
+            for (int i : lds_idx) maxL = std::max(maxL, host[i].L);
+            lds_bytes = (size_t)maxL * maxL * 4;
+        }
+        return upload_all();
+    }
+
+    // The block kernel binary-searches descriptors by block_start, so the
+    // device table lists block-path surfaces first in block order.
+    std::vector<int> order() const
+    {
+        std::vector<int> o(blk_idx);
+        o.insert(o.end(), lds_idx.begin(), lds_idx.end());
+        return o;
+    }
+
+    rsos_status upload_all()
+    {
+        const int n = (int)host.size();
+        rsos_status st = staging.ensure(sizeof(SurfDev) * n);
+        if (st != RSOS_OK) return st;
+        std::vector<int> o = order();
+        SurfDev *h = (SurfDev *)staging.host;
+        for (int k = 0; k < n; ++k) h[k] = host[o[k]];
+        return staging.copy_to(d_desc, sizeof(SurfDev) * n, stream);
+    }
+
+    rsos_status set_t_end(const std::vector<long long> &t_end)
+    {
+        for (size_t i = 0; i < host.size(); ++i) host[i].t_end = t_end[i];
+        // only t_end changes; rewriting the whole (small) table keeps t in
+        // sync too, since the host mirror of t is exact (sweep counts are
+        // deterministic)
+        return upload_all();
+    }
+
+    rsos_status launch_sweeps(long long n)
+    {
+        if (n <= 0) return RSOS_OK;
+        if (!lds_idx.empty()) {
+            lds_launcher(D)(dim3((unsigned)lds_idx.size()), lds_bytes, stream, d_desc, d_lds_idx);
+            HIP_TRY(hipGetLastError());
+        }
+        if (blk_idx.empty()) return RSOS_OK;
+        long long left = n;
+        if (stream != nullptr && n >= 2 * kGraphSweeps && !timing) {
+            if (!graph) {
+                rsos_status st = capture_graph(kGraphSweeps);
+                if (st != RSOS_OK) return st;
+            }
+            while (left >= graph_sweeps) {
+                HIP_TRY(hipGraphLaunch(graph, stream));
+                left -= graph_sweeps;
+            }
+        }
+        for (; left > 0; --left) {
+            rsos_status st = enqueue_one();
+            if (st != RSOS_OK) return st;
+        }
+        return RSOS_OK;
+    }
+
+    rsos_status enqueue_one()
+    {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            timed.push_back({e0, e1});
+            HIP_TRY(hipEventRecord(e0, stream));
+        }
+        variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size(), d_partials);
+        HIP_TRY(hipGetLastError());
+        if (timing) HIP_TRY(hipEventRecord(e1, stream));
+        hipLaunchKernelGGL((rsosk::reduce_partials<kReduceNT>), dim3((unsigned)blk_idx.size()),
+                           dim3(kReduceNT), 0, stream, d_desc, d_partials);
+        HIP_TRY(hipGetLastError());
+        return RSOS_OK;
+    }
+
+    rsos_status capture_graph(int k)
+    {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < k; ++i) {
+            variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size(), d_partials);
+            hipLaunchKernelGGL((rsosk::reduce_partials<kReduceNT>), dim3((unsigned)blk_idx.size()),
+                               dim3(kReduceNT), 0, stream, d_desc, d_partials);
+        }
+        HIP_TRY(hipStreamEndCapture(stream, &g));
+        HIP_TRY(hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphDestroy(g));
+        graph_sweeps = k;
+        return RSOS_OK;
+    }
+
+    // Reads log records of surface i for times [t_from, t_from + n).
+    rsos_status read_log(int i, long long t_from, long long n, rsos_width_t *out)
+    {
+        const SurfDev &s = host[i];
+        if (n < 0 || t_from < t0[i] || t_from + n > s.t + 1)
+            return fail(RSOS_E_INVAL, "times [%lld, %lld) outside [t0=%lld, t=%lld]", t_from,
+                        t_from + n, t0[i], s.t);
+        if (t_from + s.log_cap <= s.t && n > 0)
+            return fail(RSOS_E_INVAL, "records before t=%lld are no longer kept", s.t - s.log_cap + 1);
+        HIP_TRY(hipStreamSynchronize(stream));
+        std::vector<long long> buf((size_t)(3 * std::max<long long>(n, 1)));
+        for (long long k = 0; k < n;) {
+            const long long slot = (t_from + k) % s.log_cap;
+            const long long run = std::min(n - k, s.log_cap - slot);
+            HIP_TRY(hipMemcpy(buf.data() + 3 * k, s.log + 3 * slot, sizeof(long long) * 3 * run,
+                              hipMemcpyDeviceToHost));
+            k += run;
+        }
+        for (long long k = 0; k < n; ++k) {
+            out[k].t = t_from + k;
+            out[k].s1 = buf[3 * k];
+            out[k].s2 = buf[3 * k + 1];
+            out[k].accepted = buf[3 * k + 2];
+            out[k].w2 = w2_of(s.L, out[k].s1, out[k].s2);
+        }
+        return RSOS_OK;
+    }
+
+    rsos_status copy_heights(int i, int32_t *dst, int dst_is_device)
+    {
+        const SurfDev &s = host[i];
+        HIP_TRY(hipStreamSynchronize(stream));
+        const size_t bytes = (size_t)s.L * s.L * 4;
+        HIP_TRY(hipMemcpy(dst, s.buf[s.t & 1], bytes,
+                          dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+        return RSOS_OK;
+    }
+
+    // Writes the initial log record (time t0) of surface i.
+    rsos_status init_record(int i, long long s1, long long s2)
+    {
+        long long rec[3] = {s1, s2, 0};
+        const SurfDev &s = host[i];
+        HIP_TRY(hipMemcpy(s.log + 3 * (s.t % s.log_cap), rec, sizeof rec, hipMemcpyHostToDevice));
+        return RSOS_OK;
+    }
+
+    rsos_status read_timing(int64_t *launches, double *mean_ms, double *total_ms)
+    {
+        HIP_TRY(hipStreamSynchronize(stream));
+        double tot = 0.0;
+        for (auto &pr : timed) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+            tot += ms;
+        }
+        if (launches) *launches = (int64_t)timed.size();
+        if (total_ms) *total_ms = tot;
+        if (mean_ms) *mean_ms = timed.empty() ? 0.0 : tot / (double)timed.size();
+        clear_timing();
+        return RSOS_OK;
+    }
+
+    void clear_timing()
+    {
+        for (auto &pr : timed) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        timed.clear();
+    }
+
+    void destroy()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        else (void)hipDeviceSynchronize();
+        clear_timing();
+        if (graph) (void)hipGraphExecDestroy(graph);
+        staging.release();
+        for (void *p : owned) (void)hipFree(p);
+        owned.clear();
+    }
+};
+
+struct rsos_surface {
+    rsos_params p;
+    SurfaceGroup g;
+};
+
+struct rsos_batch {
+    std::vector<rsos_params> p;
+    SurfaceGroup g;
+};
+
+#define CHECK_HANDLE(h, grp)                                                           \
+    do {                                                                               \
+        if (!(h)) return fail(RSOS_E_INVAL, "NULL handle");                           \
+        if ((grp).failed) return fail(RSOS_E_STATE, "handle failed after a device error"); \
+    } while (0)
+
+static rsos_status mark(SurfaceGroup &g, rsos_status st)
+{
+    if (st == RSOS_E_DEVICE) g.failed = true;
+    return st;
+}
+
+extern "C" {
+
+const char *rsos_version(void) { return "rsos-gfx950 1.0"; }
+
+const char *rsos_strerror(rsos_status st)
+{
+    switch (st) {
+    case RSOS_OK: return "ok";
+    case RSOS_E_INVAL: return "invalid argument";
+    case RSOS_E_RSOS: return "initial heights violate the RSOS restriction";
+    case RSOS_E_OVERFLOW: return "heights or sums could overflow";
+    case RSOS_E_DEVICE: return "HIP runtime error";
+    case RSOS_E_NOMEM: return "out of memory";
+    case RSOS_E_STATE: return "handle failed or call out of sequence";
+    case RSOS_E_BUSY: return "no room for the job now";
+    }
+    return "unknown status";
+}
+
+const char *rsos_last_error(void) { return g_last_error.c_str(); }
+
+void rsos_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const rsosk::u32x4 r = rsosk::philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+    for (int i = 0; i < 4; ++i) out[i] = r.v[i];
+}
+
+double rsos_w2(int32_t L, int64_t s1, int64_t s2) { return w2_of(L, s1, s2); }
+
+rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, int32_t *d_work,
+                      const int32_t *h0_host, int64_t t0, int64_t log_cap, void *stream)
+{
+    if (!out) return fail(RSOS_E_INVAL, "out is NULL");
+    *out = nullptr;
+    rsos_status st = check_params(p);
+    if (st != RSOS_OK) return st;
+    if (!d_h) return fail(RSOS_E_INVAL, "d_h is NULL");
+    if (t0 < 0 || t0 >= (1ll << 32)) return fail(RSOS_E_INVAL, "t0 outside [0, 2^32)");
+    if (log_cap < 0) return fail(RSOS_E_INVAL, "log_cap < 0");
+    if (log_cap == 0) log_cap = 65536;
+    long long max_h = 0, s1 = 0, s2 = 0;
+    if (h0_host && (st = validate_h0(h0_host, p->L, p->N, &max_h, &s1, &s2)) != RSOS_OK) return st;
+    if ((st = check_overflow(*p, max_h, 0)) != RSOS_OK) return st;
+
+    rsos_surface *s = new (std::nothrow) rsos_surface();
+    if (!s) return fail(RSOS_E_NOMEM, "host allocation failed");
+    s->p = *p;
+    SurfaceGroup &g = s->g;
+    g.D = p->D;
+    g.stream = (hipStream_t)stream;
+    const size_t n = (size_t)p->L * p->L;
+    SurfDev d = {};
+    d.buf[0] = d_h;
+    d.buf[1] = d_work;
+    if (!d_work && (st = g.dev_alloc((void **)&d.buf[1], n * 4)) != RSOS_OK) { g.destroy(); delete s; return st; }
+    if ((st = g.dev_alloc((void **)&d.log, sizeof(long long) * 3 * log_cap)) != RSOS_OK) { g.destroy(); delete s; return st; }
+    d.log_cap = log_cap;
+    d.t = t0;
+    d.t_end = t0;
+    d.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.L = p->L;
+    d.N = p->N;
+    d.T = p->L / p->D;
+    g.host.push_back(d);
+    g.max_h0.push_back(max_h);
+    g.t0.push_back(t0);
+    if ((st = mark(g, g.setup())) != RSOS_OK) { g.destroy(); delete s; return st; }
+    // initial state into the buffer of parity t0
+    int32_t *cur = d.buf[t0 & 1];
+    hipError_t e = h0_host ? hipMemcpyAsync(cur, h0_host, n * 4, hipMemcpyHostToDevice, g.stream)
+                           : hipMemsetAsync(cur, 0, n * 4, g.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+    if (e != hipSuccess) {
+        g.destroy();
+        delete s;
+        return fail(RSOS_E_DEVICE, "initial copy: %s", hipGetErrorString(e));
+    }
+    if ((st = g.init_record(0, s1, s2)) != RSOS_OK) { g.destroy(); delete s; return st; }
+    *out = s;
+    return RSOS_OK;
+}
+
+rsos_status rsos_sweep(rsos_surface *s, int64_t n_mcs)
+{
+    CHECK_HANDLE(s, s->g);
+    if (n_mcs < 0) return fail(RSOS_E_INVAL, "n_mcs < 0");
+    if (n_mcs == 0) return RSOS_OK;
+    SurfaceGroup &g = s->g;
+    const long long t = g.host[0].t;
+    if (t + n_mcs > (1ll << 32)) return fail(RSOS_E_INVAL, "sweep index would exceed 2^32");
+    rsos_status st = check_overflow(s->p, g.max_h0[0], t + n_mcs - g.t0[0]);
+    if (st != RSOS_OK) return st;
+    if ((st = mark(g, g.set_t_end({t + n_mcs}))) != RSOS_OK) return st;
+    if ((st = mark(g, g.launch_sweeps(n_mcs))) != RSOS_OK) return st;
+    g.host[0].t = t + n_mcs;
+    return RSOS_OK;
+}
+
+rsos_status rsos_width(rsos_surface *s, rsos_width_t *out)
+{
+    CHECK_HANDLE(s, s->g);
+    if (!out) return fail(RSOS_E_INVAL, "out is NULL");
+    return mark(s->g, s->g.read_log(0, s->g.host[0].t, 1, out));
+}
+
+rsos_status rsos_log(rsos_surface *s, int64_t t_from, int64_t n, rsos_width_t *out)
+{
+    CHECK_HANDLE(s, s->g);
+    if (!out && n > 0) return fail(RSOS_E_INVAL, "out is NULL");
+    return mark(s->g, s->g.read_log(0, t_from, n, out));
+}
+
+rsos_status rsos_heights(rsos_surface *s, int32_t *dst, int dst_is_device)
+{
+    CHECK_HANDLE(s, s->g);
+    if (!dst) return fail(RSOS_E_INVAL, "dst is NULL");
+    return mark(s->g, s->g.copy_heights(0, dst, dst_is_device));
+}
+
+rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current)
+{
+    CHECK_HANDLE(s, s->g);
+    const SurfDev &d = s->g.host[0];
+    if (t) *t = d.t;
+    if (d_current) *d_current = d.buf[d.t & 1];
+    return RSOS_OK;
+}
+
+rsos_status rsos_timing(rsos_surface *s, int enable)
+{
+    CHECK_HANDLE(s, s->g);
+    s->g.timing = enable != 0;
+    return RSOS_OK;
+}
+
+rsos_status rsos_timing_read(rsos_surface *s, int64_t *launches, double *mean_ms, double *total_ms)
+{
+    CHECK_HANDLE(s, s->g);
+    return mark(s->g, s->g.read_timing(launches, mean_ms, total_ms));
+}
+
+rsos_status rsos_free(rsos_surface *s)
+{
+    if (!s) return RSOS_OK;
+    s->g.destroy();
+    delete s;
+    return RSOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, int32_t *d_pool,
+                            int32_t *d_work_pool, const int64_t *offsets, int64_t log_cap,
+                            void *stream)
+{
+    if (!out) return fail(RSOS_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !p || !d_pool || !offsets) return fail(RSOS_E_INVAL, "bad batch arguments");
+    if (log_cap < 0) return fail(RSOS_E_INVAL, "log_cap < 0");
+    if (log_cap == 0) log_cap = 65536;
+    rsos_status st;
+    for (int i = 0; i < n; ++i) {
+        if ((st = check_params(&p[i])) != RSOS_OK) return fail(st, "surface %d: %s", i, g_last_error.c_str());
+        if (p[i].D != p[0].D) return fail(RSOS_E_INVAL, "all surfaces of a batch share one D");
+        if (offsets[i] < 0) return fail(RSOS_E_INVAL, "negative offset");
+    }
+    // surfaces must not overlap in the pool
+    {
+        std::vector<std::pair<long long, long long>> iv;
+        for (int i = 0; i < n; ++i) iv.push_back({offsets[i], offsets[i] + (long long)p[i].L * p[i].L});
+        std::sort(iv.begin(), iv.end());
+        for (int i = 1; i < n; ++i)
+            if (iv[i].first < iv[i - 1].second) return fail(RSOS_E_INVAL, "surfaces overlap in the pool");
+    }
+    rsos_batch *b = new (std::nothrow) rsos_batch();
+    if (!b) return fail(RSOS_E_NOMEM, "host allocation failed");
+    b->p.assign(p, p + n);
+    SurfaceGroup &g = b->g;
+    g.D = p[0].D;
+    g.stream = (hipStream_t)stream;
+    long long pool_elems = 0;
+    for (int i = 0; i < n; ++i) pool_elems = std::max(pool_elems, offsets[i] + (long long)p[i].L * p[i].L);
+    int32_t *work = d_work_pool;
+    if (!work && (st = g.dev_alloc((void **)&work, (size_t)pool_elems * 4)) != RSOS_OK) { delete b; return st; }
+    long long *logs = nullptr;
+    if ((st = g.dev_alloc((void **)&logs, sizeof(long long) * 3 * log_cap * n)) != RSOS_OK) { g.destroy(); delete b; return st; }
+    for (int i = 0; i < n; ++i) {
+        SurfDev d = {};
+        d.buf[0] = d_pool + offsets[i];
+        d.buf[1] = work + offsets[i];
+        d.log = logs + 3 * log_cap * i;
+        d.log_cap = log_cap;
+        d.key0 = (uint32_t)(p[i].seed & 0xFFFFFFFFu);
+        d.key1 = (uint32_t)(p[i].seed >> 32);
+        d.L = p[i].L;
+        d.N = p[i].N;
+        d.T = p[i].L / p[i].D;
+        g.host.push_back(d);
+        g.max_h0.push_back(0);
+        g.t0.push_back(0);
+    }
+    if ((st = mark(g, g.setup())) != RSOS_OK) { g.destroy(); delete b; return st; }
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = hipMemsetAsync(g.host[i].buf[0], 0, (size_t)p[i].L * p[i].L * 4, g.stream);
+        if (e != hipSuccess) { g.destroy(); delete b; return fail(RSOS_E_DEVICE, "memset: %s", hipGetErrorString(e)); }
+    }
+    hipError_t e = hipStreamSynchronize(g.stream);
+    if (e != hipSuccess) { g.destroy(); delete b; return fail(RSOS_E_DEVICE, "sync: %s", hipGetErrorString(e)); }
+    for (int i = 0; i < n; ++i)
+        if ((st = g.init_record(i, 0, 0)) != RSOS_OK) { g.destroy(); delete b; return st; }
+    *out = b;
+    return RSOS_OK;
+}
+
+rsos_status rsos_batch_sweep(rsos_batch *b, const int64_t *n_mcs, int64_t n_all)
+{
+    CHECK_HANDLE(b, b->g);
+    SurfaceGroup &g = b->g;
+    const int n = (int)g.host.size();
+    std::vector<long long> t_end(n);
+    long long most = 0;
+    for (int i = 0; i < n; ++i) {
+        const long long k = n_mcs ? n_mcs[i] : n_all;
+        if (k < 0) return fail(RSOS_E_INVAL, "negative sweep count for surface %d", i);
+        if (g.host[i].t + k > (1ll << 32)) return fail(RSOS_E_INVAL, "sweep index would exceed 2^32");
+        rsos_status st = check_overflow(b->p[i], g.max_h0[i], g.host[i].t + k - g.t0[i]);
+        if (st != RSOS_OK) return st;
+        t_end[i] = g.host[i].t + k;
+        most = std::max(most, k);
+    }
+    if (most == 0) return RSOS_OK;
+    rsos_status st;
+    if ((st = mark(g, g.set_t_end(t_end))) != RSOS_OK) return st;
+    if ((st = mark(g, g.launch_sweeps(most))) != RSOS_OK) return st;
+    for (int i = 0; i < n; ++i) g.host[i].t = t_end[i];
+    return RSOS_OK;
+}
+
+rsos_status rsos_batch_width(rsos_batch *b, rsos_width_t *out)
+{
+    CHECK_HANDLE(b, b->g);
+    if (!out) return fail(RSOS_E_INVAL, "out is NULL");
+    for (size_t i = 0; i < b->g.host.size(); ++i) {
+        rsos_status st = mark(b->g, b->g.read_log((int)i, b->g.host[i].t, 1, out + i));
+        if (st != RSOS_OK) return st;
+    }
+    return RSOS_OK;
+}
+
+rsos_status rsos_batch_log(rsos_batch *b, int32_t i, int64_t t_from, int64_t n, rsos_width_t *out)
+{
+    CHECK_HANDLE(b, b->g);
+    if (i < 0 || i >= (int)b->g.host.size()) return fail(RSOS_E_INVAL, "surface index out of range");
+    if (!out && n > 0) return fail(RSOS_E_INVAL, "out is NULL");
+    return mark(b->g, b->g.read_log(i, t_from, n, out));
+}
+
+rsos_status rsos_batch_heights(rsos_batch *b, int32_t i, int32_t *dst, int dst_is_device)
+{
+    CHECK_HANDLE(b, b->g);
+    if (i < 0 || i >= (int)b->g.host.size()) return fail(RSOS_E_INVAL, "surface index out of range");
+    if (!dst) return fail(RSOS_E_INVAL, "dst is NULL");
+    return mark(b->g, b->g.copy_heights(i, dst, dst_is_device));
+}
+
+rsos_status rsos_batch_free(rsos_batch *b)
+{
+    if (!b) return RSOS_OK;
+    b->g.destroy();
+    delete b;
+    return RSOS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving engine (continuous batching) -- see rsos_engine.inc
+// ---------------------------------------------------------------------------
+#include "rsos_engine.inc"

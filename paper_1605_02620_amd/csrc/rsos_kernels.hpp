@@ -1,0 +1,375 @@
+// rsos_kernels.hpp -- gfx950 kernels of the RSOS deposition sweep.
+//
+// Model (Kelling, Odor & Gemming): RSOS deposition on an L x L periodic
+// lattice, accepted iff afterwards |h_i - h_j| <= N for the 4 nearest
+// neighbours (Sec. I); one sweep = L^2 attempts scheduled over D x D domains
+// whose origin moves randomly each sweep (Sec. II); per-sweep exact sums
+// S1 = sum h, S2 = sum h^2 for Eq. (2).
+//
+// Schedule of one sweep s (identical bits for any launch shape):
+//   origin (ox, oy) = Philox(0, 0, s, 2) words 0, 1 mod 2D;
+//   colour-0 tiles of the shifted frame make D^2 attempts each, then the
+//   colour-1 tiles; tile tile_id = ty*T + tx (T = L/D) in phase p takes its
+//   sites from Philox counters (j, tile_id, s, p).
+//
+// Kernels:
+//   block_sweep  one workgroup owns a TX x TY tile block of the shifted frame
+//                plus a ring of D+1 sites.  It loads the block and ring from
+//                the input buffer into LDS, recomputes the phase-0 update of
+//                the colour-0 tiles just outside the block (their inputs are
+//                all in the ring, and the update is a pure function of them),
+//                runs phase 1 on the block, stores the block into the output
+//                buffer and reduces (S1, S2, A).  Both phases of a sweep cost
+//                one read and one write of every site.
+//   reduce       sums the per-workgroup partials of each surface into its
+//                per-sweep log and advances its time.
+//   lds_run      a whole small surface (L^2 * 4 bytes fits in LDS) lives in
+//                one workgroup's LDS for many sweeps; no per-sweep launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsosk {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).  Ten rounds; each round multiplies
+// counter words 0 and 2 by the two round multipliers, mixes the high halves
+// with words 1, 3 and the key, and the key advances by the two Weyl
+// increments between rounds.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t v[4];
+};
+
+__host__ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                         uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)c0 * 0xD2511F53ull;
+        const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57ull;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    u32x4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Per-surface state shared by the kernels.  Lives in device memory; the
+// host writes it at setup and sets t_end before a run; the reduce (or
+// lds_run) kernel advances t.
+// ---------------------------------------------------------------------------
+struct SurfDev {
+    int32_t *buf[2];      // state after t sweeps is in buf[t & 1]
+    long long *log;       // 3 * log_cap int64: (S1, S2, A) of time tau at slot tau % log_cap
+    long long log_cap;
+    long long t;          // sweeps done
+    long long t_end;      // run while t < t_end
+    uint32_t key0, key1;  // Philox key = seed
+    int L, N, T;          // T = L / D
+    int nbx;              // blocks along x (block path)
+    int nblocks;          // blocks of this surface (block path)
+    int block_start;      // first global block index of this surface
+    long long part_start; // first partial-sum slot
+};
+
+template <int D>
+struct TileBits {
+    static constexpr int LOG2D = (D == 2) ? 1 : (D == 4) ? 2 : (D == 8) ? 3 : (D == 16) ? 4 : 5;
+    static constexpr int B = 2 * LOG2D;               // bits per site field
+    static constexpr int F = 32 / B;                  // fields per 32-bit word
+    static constexpr int PER = 4 * F;                 // attempts per Philox call
+    static constexpr int NCALL = (D * D + PER - 1) / PER;
+};
+
+// D^2 sequential attempts of one tile whose site (u, v) sits at LDS index
+// base + v*RW + u (a rectangular LDS region with row stride RW, neighbours
+// at +-1 and +-RW).  Returns the accepted count.
+template <int D, int RW>
+__device__ __forceinline__ int tile_attempts(int32_t *lds, int base, uint32_t tile_id, uint32_t s,
+                                             uint32_t p, int N, uint32_t k0, uint32_t k1)
+{
+    using TB = TileBits<D>;
+    int acc = 0;
+#pragma unroll 1
+    for (int j = 0; j < TB::NCALL; ++j) {
+        const u32x4 r = philox4x32_10((uint32_t)j, tile_id, s, p, k0, k1);
+#pragma unroll
+        for (int q = 0; q < TB::PER; ++q) {
+            if (j * TB::PER + q < D * D) {
+                const uint32_t f = (r.v[q / TB::F] >> ((q % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
+                const int idx = base + (int)(f >> TB::LOG2D) * RW + (int)(f & (D - 1));
+                const int c = lds[idx];
+                const int m = min(min(lds[idx - 1], lds[idx + 1]), min(lds[idx - RW], lds[idx + RW]));
+                // h_c + 1 - h_j <= N for every neighbour j; the lower side
+                // cannot fail because |h_c - h_j| <= N held before.
+                const int ok = (c - m) < N;
+                lds[idx] = c + ok;
+                acc += ok;
+            }
+        }
+    }
+    return acc;
+}
+
+// XCD-aware renumbering: the dispatcher hands consecutive workgroup ids to
+// the 8 XCDs in turn; renumber so that each XCD walks one contiguous range
+// of blocks (neighbouring blocks share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int wg, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int x = wg & 7, j = wg >> 3;
+    return x * q + min(x, r) + j;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_reduce3(long long &a, long long &b, long long &c)
+{
+    __shared__ long long red[3][NT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (NT > 64) {
+        if (l == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < NT / 64; ++i) { a += red[0][i]; b += red[1][i]; c += red[2][i]; }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block_sweep: one sweep for every active surface of the descriptor table.
+// Requirements checked on the host: T % TX == 0, T % TY == 0, TX and TY
+// even, region (TX*D + 2D + 2) x (TY*D + 2D + 2) no wider than L.
+// ---------------------------------------------------------------------------
+template <int D, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf,
+                                                  long long *__restrict__ partials)
+{
+    constexpr int RING = D + 1;
+    constexpr int RW = TX * D + 2 * RING;
+    constexpr int RH = TY * D + 2 * RING;
+    constexpr int HALF = TX * TY / 2;
+    constexpr int P0 = HALF + TX + TY;
+    __shared__ int32_t lds[RW * RH];
+
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nsurf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].block_start <= lb) lo = mid; else hi = mid - 1;
+    }
+    const SurfDev &d = descs[lo];
+    const long long t = d.t;
+    if (t >= d.t_end) return;
+
+    const int L = d.L, N = d.N, T = d.T;
+    const uint32_t s = (uint32_t)t;
+    const uint32_t k0 = d.key0, k1 = d.key1;
+    const int32_t *__restrict__ hin = d.buf[t & 1];
+    int32_t *__restrict__ hout = d.buf[(t + 1) & 1];
+
+    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
+    const int ox = (int)(org.v[0] % (2u * D));
+    const int oy = (int)(org.v[1] % (2u * D));
+
+    const int b = lb - d.block_start;
+    const int bx = b % d.nbx, by = b / d.nbx;
+    int gx0 = ox + bx * TX * D - RING;
+    int gy0 = oy + by * TY * D - RING;
+    if (gx0 < 0) gx0 += L;
+    if (gy0 < 0) gy0 += L;
+
+    // load block + ring (rows of the region are contiguous runs in memory)
+    for (int i = threadIdx.x; i < RW * RH; i += NT) {
+        const int r = i / RW, c = i - r * RW;
+        int gy = gy0 + r; if (gy >= L) gy -= L;
+        int gx = gx0 + c; if (gx >= L) gx -= L;
+        lds[i] = hin[(size_t)gy * L + gx];
+    }
+    __syncthreads();
+
+    long long acc = 0;
+    // phase 0: colour-0 tiles of the block, then the colour-0 ring tiles that
+    // touch the block's colour-1 border tiles
+    for (int k = threadIdx.x; k < P0; k += NT) {
+        int ltx, lty;
+        if (k < HALF) {
+            lty = k / (TX / 2);
+            ltx = 2 * (k % (TX / 2)) + (lty & 1);
+        } else {
+            const int g = k - HALF;
+            if (g < TX / 2) { lty = -1; ltx = 2 * g + 1; }
+            else if (g < TX) { lty = TY; ltx = 2 * (g - TX / 2); }
+            else if (g < TX + TY / 2) { ltx = -1; lty = 2 * (g - TX) + 1; }
+            else { ltx = TX; lty = 2 * (g - TX - TY / 2); }
+        }
+        int gtx = bx * TX + ltx, gty = by * TY + lty;
+        gtx = gtx < 0 ? gtx + T : (gtx >= T ? gtx - T : gtx);
+        gty = gty < 0 ? gty + T : (gty >= T ? gty - T : gty);
+        const int base = (lty * D + RING) * RW + ltx * D + RING;
+        const int a = tile_attempts<D, RW>(lds, base, (uint32_t)(gty * T + gtx), s, 0u, N, k0, k1);
+        if (k < HALF) acc += a;
+    }
+    __syncthreads();
+    // phase 1: colour-1 tiles of the block
+    for (int k = threadIdx.x; k < HALF; k += NT) {
+        const int lty = k / (TX / 2);
+        const int ltx = 2 * (k % (TX / 2)) + 1 - (lty & 1);
+        const int gtx = bx * TX + ltx, gty = by * TY + lty;
+        const int base = (lty * D + RING) * RW + ltx * D + RING;
+        acc += tile_attempts<D, RW>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1);
+    }
+    __syncthreads();
+
+    // store the block and reduce its sums
+    long long s1 = 0, s2 = 0;
+    constexpr int BW = TX * D, BH = TY * D;
+    for (int i = threadIdx.x; i < BW * BH; i += NT) {
+        const int r = i / BW, c = i - r * BW;
+        const int v = lds[(r + RING) * RW + c + RING];
+        int gy = gy0 + RING + r; if (gy >= L) gy -= L;
+        int gx = gx0 + RING + c; if (gx >= L) gx -= L;
+        hout[(size_t)gy * L + gx] = v;
+        s1 += v;
+        s2 += (long long)v * v;
+    }
+    block_reduce3<NT>(s1, s2, acc);
+    if (threadIdx.x == 0) {
+        long long *p = partials + 3 * (d.part_start + b);
+        p[0] = s1;
+        p[1] = s2;
+        p[2] = acc;
+    }
+}
+
+// Sums each active surface's partials into its log and advances t.
+template <int NT>
+__global__ __launch_bounds__(NT) void reduce_partials(SurfDev *__restrict__ descs,
+                                                      const long long *__restrict__ partials)
+{
+    SurfDev &d = descs[blockIdx.x];
+    const long long t = d.t;
+    if (t >= d.t_end) return;
+    long long a = 0, b = 0, c = 0;
+    const long long *p = partials + 3 * d.part_start;
+    for (int i = threadIdx.x; i < d.nblocks; i += NT) {
+        a += p[3 * i];
+        b += p[3 * i + 1];
+        c += p[3 * i + 2];
+    }
+    block_reduce3<NT>(a, b, c);
+    if (threadIdx.x == 0) {
+        long long *e = d.log + 3 * ((t + 1) % d.log_cap);
+        e[0] = a;
+        e[1] = b;
+        e[2] = c;
+        d.t = t + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lds_run: surfaces small enough to live in LDS, one workgroup each, all
+// their sweeps in one launch.  which[] lists descriptor indices; the LDS is
+// L_max^2 int32 of dynamic shared memory.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ int tile_attempts_torus(int32_t *h, int L, int x0, int y0,
+                                                   uint32_t tile_id, uint32_t s, uint32_t p, int N,
+                                                   uint32_t k0, uint32_t k1)
+{
+    using TB = TileBits<D>;
+    int acc = 0;
+#pragma unroll 1
+    for (int j = 0; j < TB::NCALL; ++j) {
+        const u32x4 r = philox4x32_10((uint32_t)j, tile_id, s, p, k0, k1);
+#pragma unroll
+        for (int q = 0; q < TB::PER; ++q) {
+            if (j * TB::PER + q < D * D) {
+                const uint32_t f = (r.v[q / TB::F] >> ((q % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
+                int x = x0 + (int)(f & (D - 1));
+                int y = y0 + (int)(f >> TB::LOG2D);
+                if (x >= L) x -= L;
+                if (y >= L) y -= L;
+                const int xl = x == 0 ? L - 1 : x - 1, xr = x == L - 1 ? 0 : x + 1;
+                const int yu = y == 0 ? L - 1 : y - 1, yd = y == L - 1 ? 0 : y + 1;
+                const int c = h[y * L + x];
+                const int m = min(min(h[y * L + xl], h[y * L + xr]), min(h[yu * L + x], h[yd * L + x]));
+                const int ok = (c - m) < N;
+                h[y * L + x] = c + ok;
+                acc += ok;
+            }
+        }
+    }
+    return acc;
+}
+
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void lds_run(SurfDev *__restrict__ descs, const int *__restrict__ which)
+{
+    extern __shared__ int32_t lat[];
+    SurfDev &d = descs[which[blockIdx.x]];
+    long long t = d.t;
+    const long long t_end = d.t_end;
+    if (t >= t_end) return;
+    const int L = d.L, N = d.N, T = d.T;
+    const int n = L * L;
+    const uint32_t k0 = d.key0, k1 = d.key1;
+    {
+        const int32_t *src = d.buf[t & 1];
+        for (int i = threadIdx.x; i < n; i += NT) lat[i] = src[i];
+    }
+    __syncthreads();
+    const int half = T * T / 2;
+    for (; t < t_end; ++t) {
+        const uint32_t s = (uint32_t)t;
+        const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
+        const int ox = (int)(org.v[0] % (2u * D));
+        const int oy = (int)(org.v[1] % (2u * D));
+        long long acc = 0;
+        for (int p = 0; p < 2; ++p) {
+            for (int k = threadIdx.x; k < half; k += NT) {
+                const int ty = k / (T / 2);
+                const int tx = 2 * (k % (T / 2)) + ((ty + p) & 1);
+                acc += tile_attempts_torus<D>(lat, L, ox + tx * D, oy + ty * D,
+                                              (uint32_t)(ty * T + tx), s, (uint32_t)p, N, k0, k1);
+            }
+            __syncthreads();
+        }
+        long long s1 = 0, s2 = 0;
+        for (int i = threadIdx.x; i < n; i += NT) {
+            const long long v = lat[i];
+            s1 += v;
+            s2 += v * v;
+        }
+        block_reduce3<NT>(s1, s2, acc);
+        if (threadIdx.x == 0) {
+            long long *e = d.log + 3 * ((t + 1) % d.log_cap);
+            e[0] = s1;
+            e[1] = s2;
+            e[2] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        int32_t *dst = d.buf[t_end & 1];
+        for (int i = threadIdx.x; i < n; i += NT) dst[i] = lat[i];
+    }
+    if (threadIdx.x == 0) d.t = t_end;
+}
+
+}  // namespace rsosk
