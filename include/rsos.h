@@ -180,41 +180,53 @@ rsos_status rsos_batch_free(rsos_batch *b);
 enum { RSOS_JOB_QUEUED = 0, RSOS_JOB_RUNNING = 1, RSOS_JOB_DONE = 2, RSOS_JOB_CANCELLED = 3 };
 
 /* Creates an engine over a caller-owned device pool of pool_bytes bytes.
- * Jobs are admitted in arrival order while their footprint (2 L^2 int32
- * buffers, 256-byte aligned) fits in the free pool and fewer than
- * max_running jobs run.  Every running job advances one sweep per tick; a
- * tick is one launch over all running jobs. */
+ * Jobs are admitted in arrival order (strict FIFO) while their footprint
+ * (two L^2 int32 lattices, each 256-byte aligned) fits in the free part of
+ * the pool and fewer than max_running jobs run.  Every running job advances
+ * one sweep per tick; a tick is one launch over all running jobs (jobs whose
+ * L^2 int32 fit in LDS run on a second stream).  Ticks are issued in chunks
+ * of up to 16; admission, retirement and result collection happen between
+ * chunks.  d_pool must be 256-byte aligned; all jobs share the engine's D. */
 rsos_status rsos_engine_create(rsos_engine **out, void *d_pool, int64_t pool_bytes,
                                int32_t max_running, int32_t D, void *stream);
 
-/* Queues a job: parameters p (p->D must equal the engine's D), t_max
- * sweeps, and the sweep times (1 <= t <= t_max, increasing) at which its
- * width record is kept.  *job_id receives the id.  RSOS_E_INVAL if the job
- * could never fit the pool. */
+/* Flags of rsos_engine_submit. */
+enum { RSOS_JOB_KEEP_HEIGHTS = 1 };
+
+/* Queues a job: parameters p (p->D must equal the engine's D), t_max >= 1
+ * sweeps, and the sweep times (1 <= t <= t_max, strictly increasing) whose
+ * width records are kept.  With RSOS_JOB_KEEP_HEIGHTS the final heights
+ * are copied to host memory when the job finishes.  *job_id receives the
+ * id.  RSOS_E_INVAL if the job could never fit the pool. */
 rsos_status rsos_engine_submit(rsos_engine *e, const rsos_params *p, int64_t t_max,
-                               const int64_t *sample_t, int32_t n_samples, int64_t *job_id);
+                               const int64_t *sample_t, int32_t n_samples, int32_t flags,
+                               int64_t *job_id);
 
 /* Admits what fits, then runs up to max_ticks ticks (stopping early when
  * nothing runs), retiring finished jobs and admitting queued ones between
- * ticks.  *n_finished (may be NULL) receives the jobs that finished. */
+ * chunks.  *n_finished (may be NULL) receives the jobs that finished. */
 rsos_status rsos_engine_step(rsos_engine *e, int64_t max_ticks, int32_t *n_finished);
 
 /* State of a job (RSOS_JOB_*) and its current sweep count. */
 rsos_status rsos_engine_poll(rsos_engine *e, int64_t job_id, int32_t *state, int64_t *t);
 
 /* Results of a finished job: its n_samples width records (at the requested
- * times) and, if heights_host is non-NULL, its final int32[L*L] heights.
- * A job's results stay until rsos_engine_release. */
+ * times; a cancelled job fills only the records it reached and sets the
+ * rest to t = -1) and, if heights_host is non-NULL and the job kept them,
+ * its final int32[L*L] heights.  *latency_s (may be NULL) receives the time
+ * from submission to completion in seconds.  Results stay until
+ * rsos_engine_release. */
 rsos_status rsos_engine_result(rsos_engine *e, int64_t job_id, rsos_width_t *samples,
-                               int32_t *heights_host);
+                               int32_t *heights_host, double *latency_s);
 
-/* Drops a queued or running job (its memory is freed at the next tick). */
+/* Drops a queued or running job; a running job's memory is freed at the
+ * next chunk boundary. */
 rsos_status rsos_engine_cancel(rsos_engine *e, int64_t job_id);
 
 /* Forgets a finished or cancelled job's stored results. */
 rsos_status rsos_engine_release(rsos_engine *e, int64_t job_id);
 
-/* Counters: [0] queued, [1] running, [2] finished, [3] bytes in use,
+/* Counters: [0] queued, [1] running, [2] finished, [3] pool bytes in use,
  * [4] ticks, [5] attempted site updates so far. */
 rsos_status rsos_engine_stats(rsos_engine *e, int64_t out[6]);
 

@@ -55,10 +55,10 @@ SIGNATURES = [
     ("rsos_batch_heights", c_i32, [c_vp, c_i32, c_vp, ctypes.c_int]),
     ("rsos_batch_free", c_i32, [c_vp]),
     ("rsos_engine_create", c_i32, [P(c_vp), c_vp, c_i64, c_i32, c_i32, c_vp]),
-    ("rsos_engine_submit", c_i32, [c_vp, P(Params), c_i64, P(c_i64), c_i32, P(c_i64)]),
+    ("rsos_engine_submit", c_i32, [c_vp, P(Params), c_i64, P(c_i64), c_i32, c_i32, P(c_i64)]),
     ("rsos_engine_step", c_i32, [c_vp, c_i64, P(c_i32)]),
     ("rsos_engine_poll", c_i32, [c_vp, c_i64, P(c_i32), P(c_i64)]),
-    ("rsos_engine_result", c_i32, [c_vp, c_i64, P(Width), c_vp]),
+    ("rsos_engine_result", c_i32, [c_vp, c_i64, P(Width), c_vp, P(ctypes.c_double)]),
     ("rsos_engine_cancel", c_i32, [c_vp, c_i64]),
     ("rsos_engine_release", c_i32, [c_vp, c_i64]),
     ("rsos_engine_stats", c_i32, [c_vp, P(c_i64)]),

@@ -1,7 +1,7 @@
 // rsos.hip -- host runtime and C ABI of librsos.so (see include/rsos.h).
 //
 // Launch plan per sweep: block_sweep over every tile block of every active
-// surface, then reduce_partials (one workgroup per surface).  Both kernels
+// surface, then reduce_acc (one workgroup per surface).  Both kernels
 // read the surface time t from device memory, so a captured hipGraph of K
 // sweeps replays for any t.  Surfaces whose L^2 int32 fit in LDS run all
 // their sweeps in one lds_run launch instead.
@@ -44,59 +44,62 @@ rsos_status fail(rsos_status st, const char *fmt, ...)
     } while (0)
 
 constexpr int kLdsMaxBytes = 64 * 1024;  // lds_run: whole surface in LDS
-constexpr int kReduceNT = 256;
 constexpr int kGraphSweeps = 32;
 
 // ---------------------------------------------------------------------------
 // Block-kernel variants.  The tile block shape never changes results; it
 // only has to tile the lattice: T % TX == 0, T % TY == 0, region <= L.
 // ---------------------------------------------------------------------------
-typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int, long long *);
+typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int);
 
-template <int D, int TX, int TY, int NT>
-void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, long long *p)
+template <int D, int TX, int TY, int NT, typename E>
+void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT>), grid, dim3(NT), 0, st, d, n, p);
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E>), grid, dim3(NT), 0, st, d, n);
 }
 
 struct Variant {
-    int D, TX, TY, NT;
+    int D, TX, TY, NT, elem;  // elem: LDS bytes per site (2 = int16 offsets, 4 = int32)
     BlockLaunch launch;
 };
 
+#define V16(D, TX, TY, NT) {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t>}
+#define V32(D, TX, TY, NT) {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t>}
+// In order of preference; the first one that fits every surface is used.
 const Variant kVariants[] = {
-    {2, 32, 32, 256, launch_block<2, 32, 32, 256>},
-    {2, 2, 2, 64, launch_block<2, 2, 2, 64>},
-    {4, 16, 16, 128, launch_block<4, 16, 16, 128>},
-    {4, 2, 2, 64, launch_block<4, 2, 2, 64>},
-    {8, 16, 8, 64, launch_block<8, 16, 8, 64>},
-    {8, 8, 8, 64, launch_block<8, 8, 8, 64>},
-    {8, 2, 2, 64, launch_block<8, 2, 2, 64>},
-    {16, 4, 4, 64, launch_block<16, 4, 4, 64>},
-    {16, 2, 2, 64, launch_block<16, 2, 2, 64>},
+    V16(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
+    V16(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64),
+    V16(8, 16, 8, 128), V16(8, 16, 16, 192), V16(8, 32, 8, 192), V16(8, 8, 8, 64), V32(8, 16, 8, 128), V32(8, 8, 8, 64), V32(8, 2, 2, 64),
+    V16(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
 };
+#undef V16
+#undef V32
 
-bool variant_fits(const Variant &v, int L)
+bool variant_fits(const Variant &v, int L, int N)
 {
     const int T = L / v.D;
     const int rw = v.TX * v.D + 2 * (v.D + 1), rh = v.TY * v.D + 2 * (v.D + 1);
-    return T % v.TX == 0 && T % v.TY == 0 && rw <= L && rh <= L;
+    const int rwl = (rw + 6) & ~3;
+    if (T % v.TX != 0 || T % v.TY != 0 || rwl > L || rh > L) return false;
+    // int16 staging: every staged value within 32767 of the block reference
+    if (v.elem == 2 && (long long)N * (rw + rh + 4) + v.D * v.D > 32767) return false;
+    return true;
 }
 
-// First fitting variant for D that fits every L in Ls (optionally forced
-// by the RSOS_VARIANT environment variable "TXxTY").
-const Variant *pick_variant(int D, const std::vector<int> &Ls)
+// First fitting variant for D that fits every (L, N) (optionally forced by
+// the RSOS_VARIANT environment variable "TXxTYxNTxELEM", e.g. "16x8x128x2").
+const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN)
 {
     const char *force = getenv("RSOS_VARIANT");
     for (const Variant &v : kVariants) {
         if (v.D != D) continue;
         if (force) {
-            char want[32];
-            snprintf(want, sizeof want, "%dx%d", v.TX, v.TY);
+            char want[48];
+            snprintf(want, sizeof want, "%dx%dx%dx%d", v.TX, v.TY, v.NT, v.elem);
             if (strcmp(force, want) != 0) continue;
         }
         bool ok = true;
-        for (int L : Ls) ok = ok && variant_fits(v, L);
+        for (auto &ln : LN) ok = ok && variant_fits(v, ln.first, ln.second);
         if (ok) return &v;
     }
     return nullptr;
@@ -229,7 +232,7 @@ struct SurfaceGroup {
     std::vector<SurfDev> host;         // host mirror (t, t_end kept current)
     std::vector<long long> max_h0, t0; // per surface
     SurfDev *d_desc = nullptr;
-    long long *d_partials = nullptr;
+    long long *d_acc = nullptr;        // kAccSlots x 3 accumulators per block-path surface
     std::vector<int> lds_idx, blk_idx; // surfaces on each path
     int *d_lds_idx = nullptr;
     const Variant *variant = nullptr;
@@ -255,13 +258,16 @@ struct SurfaceGroup {
     rsos_status setup()
     {
         const int n = (int)host.size();
-        std::vector<int> Ls;
+        std::vector<std::pair<int, int>> LN;
         for (int i = 0; i < n; ++i) {
             if (uses_lds(host[i].L)) lds_idx.push_back(i);
-            else { blk_idx.push_back(i); Ls.push_back(host[i].L); }
+            else { blk_idx.push_back(i); LN.push_back({host[i].L, host[i].N}); }
+            for (int k = 0; k < 2; ++k)
+                if (((uintptr_t)host[i].buf[k] & 15) != 0)
+                    return fail(RSOS_E_INVAL, "height buffers must be 16-byte aligned");
         }
         if (!blk_idx.empty()) {
-            variant = pick_variant(D, Ls);
+            variant = pick_variant(D, LN);
             if (!variant) return fail(RSOS_E_INVAL, "no tile-block shape fits these lattice sizes");
         }
         // block path surfaces first in the table, sorted by block_start
@@ -272,7 +278,6 @@ struct SurfaceGroup {
             s.nbx = T / variant->TX;
             s.nblocks = s.nbx * (T / variant->TY);
             s.block_start = (int)blocks;
-            s.part_start = blocks;
             blocks += s.nblocks;
             if (blocks > (1ll << 30)) return fail(RSOS_E_INVAL, "too many tile blocks");
         }
@@ -281,13 +286,16 @@ struct SurfaceGroup {
             host[i].nbx = 0;
             host[i].nblocks = 0;
             host[i].block_start = 1 << 30;  // never matched by a block workgroup
-            host[i].part_start = 0;
         }
         rsos_status st;
         if ((st = dev_alloc((void **)&d_desc, sizeof(SurfDev) * n)) != RSOS_OK) return st;
-        if (total_blocks > 0 &&
-            (st = dev_alloc((void **)&d_partials, sizeof(long long) * 3 * total_blocks)) != RSOS_OK)
-            return st;
+        if (!blk_idx.empty()) {
+            const size_t bytes = sizeof(long long) * 3 * rsosk::kAccSlots * blk_idx.size();
+            if ((st = dev_alloc((void **)&d_acc, bytes)) != RSOS_OK) return st;
+            HIP_TRY(hipMemset(d_acc, 0, bytes));
+            for (size_t k = 0; k < blk_idx.size(); ++k)
+                host[blk_idx[k]].acc = d_acc + 3 * rsosk::kAccSlots * k;
+        }
         if (!lds_idx.empty()) {
             if ((st = dev_alloc((void **)&d_lds_idx, sizeof(int) * lds_idx.size())) != RSOS_OK) return st;
             // device-table positions of the LDS-path surfaces (they follow
@@ -366,11 +374,11 @@ struct SurfaceGroup {
             timed.push_back({e0, e1});
             HIP_TRY(hipEventRecord(e0, stream));
         }
-        variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size(), d_partials);
+        variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size());
         HIP_TRY(hipGetLastError());
         if (timing) HIP_TRY(hipEventRecord(e1, stream));
-        hipLaunchKernelGGL((rsosk::reduce_partials<kReduceNT>), dim3((unsigned)blk_idx.size()),
-                           dim3(kReduceNT), 0, stream, d_desc, d_partials);
+        hipLaunchKernelGGL(rsosk::reduce_acc, dim3((unsigned)blk_idx.size()), dim3(64), 0, stream,
+                           d_desc);
         HIP_TRY(hipGetLastError());
         return RSOS_OK;
     }
@@ -380,9 +388,9 @@ struct SurfaceGroup {
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < k; ++i) {
-            variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size(), d_partials);
-            hipLaunchKernelGGL((rsosk::reduce_partials<kReduceNT>), dim3((unsigned)blk_idx.size()),
-                               dim3(kReduceNT), 0, stream, d_desc, d_partials);
+            variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size());
+            hipLaunchKernelGGL(rsosk::reduce_acc, dim3((unsigned)blk_idx.size()), dim3(64), 0,
+                               stream, d_desc);
         }
         HIP_TRY(hipStreamEndCapture(stream, &g));
         HIP_TRY(hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));

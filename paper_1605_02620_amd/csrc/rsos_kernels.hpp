@@ -15,14 +15,17 @@
 // Kernels:
 //   block_sweep  one workgroup owns a TX x TY tile block of the shifted frame
 //                plus a ring of D+1 sites.  It loads the block and ring from
-//                the input buffer into LDS, recomputes the phase-0 update of
-//                the colour-0 tiles just outside the block (their inputs are
-//                all in the ring, and the update is a pure function of them),
-//                runs phase 1 on the block, stores the block into the output
-//                buffer and reduces (S1, S2, A).  Both phases of a sweep cost
-//                one read and one write of every site.
-//   reduce       sums the per-workgroup partials of each surface into its
-//                per-sweep log and advances its time.
+//                the input buffer into LDS (aligned 16-byte chunks, int16
+//                offsets from a per-block reference height when N is small
+//                enough), recomputes the phase-0 update of the colour-0 tiles
+//                just outside the block (their inputs are all in the ring,
+//                and the update is a pure function of them), runs phase 1 on
+//                the block, stores the block into the output buffer and adds
+//                its (S1, S2, A) to one of the surface's 64 accumulator
+//                slots.  Both phases of a sweep cost one read and one write
+//                of every site.
+//   reduce_acc   folds each surface's accumulators into its per-sweep log,
+//                clears them and advances its time.
 //   lds_run      a whole small surface (L^2 * 4 bytes fits in LDS) lives in
 //                one workgroup's LDS for many sweeps; no per-sweep launch.
 #pragma once
@@ -68,9 +71,12 @@ __host__ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1
 // host writes it at setup and sets t_end before a run; the reduce (or
 // lds_run) kernel advances t.
 // ---------------------------------------------------------------------------
+constexpr int kAccSlots = 64;  // per-surface spread of the (S1, S2, A) atomics
+
 struct SurfDev {
     int32_t *buf[2];      // state after t sweeps is in buf[t & 1]
     long long *log;       // 3 * log_cap int64: (S1, S2, A) of time tau at slot tau % log_cap
+    long long *acc;       // 3 * kAccSlots int64 accumulators, zero between sweeps
     long long log_cap;
     long long t;          // sweeps done
     long long t_end;      // run while t < t_end
@@ -79,7 +85,6 @@ struct SurfDev {
     int nbx;              // blocks along x (block path)
     int nblocks;          // blocks of this surface (block path)
     int block_start;      // first global block index of this surface
-    long long part_start; // first partial-sum slot
 };
 
 template <int D>
@@ -91,11 +96,28 @@ struct TileBits {
     static constexpr int NCALL = (D * D + PER - 1) / PER;
 };
 
+// Geometry of a TX x TY tile block with its ring of D+1 sites, as staged in
+// LDS: region rows of RW sites stored with pitch RWL elements, shifted right
+// by the alignment pad (0..3) of the region's first column so that every
+// global load is an aligned 16-byte chunk.
+template <int D, int TX, int TY>
+struct BlockGeom {
+    static constexpr int RING = D + 1;
+    static constexpr int RW = TX * D + 2 * RING;
+    static constexpr int RH = TY * D + 2 * RING;
+    static constexpr int RWL = (RW + 3 + 3) & ~3;
+    static constexpr int CH = RWL / 4;
+    static constexpr int HALF = TX * TY / 2;
+    static constexpr int P0 = HALF + TX + TY;
+    static constexpr int BW = TX * D, BH = TY * D;
+};
+
 // D^2 sequential attempts of one tile whose site (u, v) sits at LDS index
-// base + v*RW + u (a rectangular LDS region with row stride RW, neighbours
-// at +-1 and +-RW).  Returns the accepted count.
-template <int D, int RW>
-__device__ __forceinline__ int tile_attempts(int32_t *lds, int base, uint32_t tile_id, uint32_t s,
+// base + v*P + u (neighbours at +-1 and +-P).  E is the LDS element type:
+// int16 holds heights relative to a per-block reference, int32 raw heights.
+// Returns the accepted count.
+template <int D, int P, typename E>
+__device__ __forceinline__ int tile_attempts(E *lds, int base, uint32_t tile_id, uint32_t s,
                                              uint32_t p, int N, uint32_t k0, uint32_t k1)
 {
     using TB = TileBits<D>;
@@ -107,13 +129,14 @@ __device__ __forceinline__ int tile_attempts(int32_t *lds, int base, uint32_t ti
         for (int q = 0; q < TB::PER; ++q) {
             if (j * TB::PER + q < D * D) {
                 const uint32_t f = (r.v[q / TB::F] >> ((q % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
-                const int idx = base + (int)(f >> TB::LOG2D) * RW + (int)(f & (D - 1));
+                const int idx = base + (int)(f >> TB::LOG2D) * P + (int)(f & (D - 1));
                 const int c = lds[idx];
-                const int m = min(min(lds[idx - 1], lds[idx + 1]), min(lds[idx - RW], lds[idx + RW]));
+                const int m = min(min((int)lds[idx - 1], (int)lds[idx + 1]),
+                                  min((int)lds[idx - P], (int)lds[idx + P]));
                 // h_c + 1 - h_j <= N for every neighbour j; the lower side
                 // cannot fail because |h_c - h_j| <= N held before.
                 const int ok = (c - m) < N;
-                lds[idx] = c + ok;
+                lds[idx] = (E)(c + ok);
                 acc += ok;
             }
         }
@@ -131,16 +154,22 @@ __device__ __forceinline__ int xcd_remap(int wg, int n)
     return x * q + min(x, r) + j;
 }
 
-template <int NT>
-__device__ __forceinline__ void block_reduce3(long long &a, long long &b, long long &c)
+__device__ __forceinline__ void wave_reduce3(long long &a, long long &b, long long &c)
 {
-    __shared__ long long red[3][NT / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off, 64);
         b += __shfl_xor(b, off, 64);
         c += __shfl_xor(c, off, 64);
     }
+}
+
+// Result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_reduce3(long long &a, long long &b, long long &c)
+{
+    __shared__ long long red[3][NT / 64 > 0 ? NT / 64 : 1];
+    wave_reduce3(a, b, c);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (NT > 64) {
         if (l == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; }
@@ -151,21 +180,37 @@ __device__ __forceinline__ void block_reduce3(long long &a, long long &b, long l
     }
 }
 
+template <typename E>
+__device__ __forceinline__ void lds_put4(E *dst, const int4 v, int ref);
+
+template <>
+__device__ __forceinline__ void lds_put4<int16_t>(int16_t *dst, const int4 v, int ref)
+{
+    const uint32_t lo = (uint32_t)(uint16_t)(v.x - ref) | ((uint32_t)(uint16_t)(v.y - ref) << 16);
+    const uint32_t hi = (uint32_t)(uint16_t)(v.z - ref) | ((uint32_t)(uint16_t)(v.w - ref) << 16);
+    *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
+}
+
+template <>
+__device__ __forceinline__ void lds_put4<int32_t>(int32_t *dst, const int4 v, int)
+{
+    *reinterpret_cast<int4 *>(dst) = v;
+}
+
 // ---------------------------------------------------------------------------
 // block_sweep: one sweep for every active surface of the descriptor table.
 // Requirements checked on the host: T % TX == 0, T % TY == 0, TX and TY
-// even, region (TX*D + 2D + 2) x (TY*D + 2D + 2) no wider than L.
+// even, RWL <= L, RH <= L, 16-byte aligned buffers, and for E = int16
+// N * (RW + RH + 4) + D^2 <= 32767 (every staged value stays within int16
+// of the reference: any two region sites are joined by a path of at most
+// RW + RH - 2 bonds, each of height difference <= N, and no site gains
+// more than D^2 in a sweep).
 // ---------------------------------------------------------------------------
-template <int D, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf,
-                                                  long long *__restrict__ partials)
+template <int D, int TX, int TY, int NT, typename E>
+__global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf)
 {
-    constexpr int RING = D + 1;
-    constexpr int RW = TX * D + 2 * RING;
-    constexpr int RH = TY * D + 2 * RING;
-    constexpr int HALF = TX * TY / 2;
-    constexpr int P0 = HALF + TX + TY;
-    __shared__ int32_t lds[RW * RH];
+    using G = BlockGeom<D, TX, TY>;
+    __shared__ __attribute__((aligned(16))) E lds[G::RWL * G::RH];
 
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     int lo = 0, hi = nsurf - 1;
@@ -189,30 +234,51 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
 
     const int b = lb - d.block_start;
     const int bx = b % d.nbx, by = b / d.nbx;
-    int gx0 = ox + bx * TX * D - RING;
-    int gy0 = oy + by * TY * D - RING;
+    int gx0 = ox + bx * TX * D - G::RING;
+    int gy0 = oy + by * TY * D - G::RING;
     if (gx0 < 0) gx0 += L;
     if (gy0 < 0) gy0 += L;
+    const int cpad = gx0 & 3;
+    const int gxa = gx0 - cpad;
+    const int ref = (sizeof(E) == 2) ? hin[(size_t)gy0 * L + gx0] : 0;
 
-    // load block + ring (rows of the region are contiguous runs in memory)
-    for (int i = threadIdx.x; i < RW * RH; i += NT) {
-        const int r = i / RW, c = i - r * RW;
-        int gy = gy0 + r; if (gy >= L) gy -= L;
-        int gx = gx0 + c; if (gx >= L) gx -= L;
-        lds[i] = hin[(size_t)gy * L + gx];
+    // load the region in aligned 16-byte chunks, U chunks in flight per thread
+    constexpr int NCH = G::CH * G::RH;
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < NCH; i0 += NT * U) {
+        int4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+            if (i < NCH) {
+                const int r = i / G::CH, cc = i - r * G::CH;
+                int gy = gy0 + r; if (gy >= L) gy -= L;
+                int gx = gxa + 4 * cc; if (gx >= L) gx -= L;
+                v[u] = *reinterpret_cast<const int4 *>(hin + (size_t)gy * L + gx);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+            if (i < NCH) {
+                const int r = i / G::CH, cc = i - r * G::CH;
+                lds_put4<E>(lds + r * G::RWL + 4 * cc, v[u], ref);
+            }
+        }
     }
     __syncthreads();
 
+    const int off = G::RING + cpad;  // LDS column of block column 0 is off + ...
     long long acc = 0;
     // phase 0: colour-0 tiles of the block, then the colour-0 ring tiles that
     // touch the block's colour-1 border tiles
-    for (int k = threadIdx.x; k < P0; k += NT) {
+    for (int k = threadIdx.x; k < G::P0; k += NT) {
         int ltx, lty;
-        if (k < HALF) {
+        if (k < G::HALF) {
             lty = k / (TX / 2);
             ltx = 2 * (k % (TX / 2)) + (lty & 1);
         } else {
-            const int g = k - HALF;
+            const int g = k - G::HALF;
             if (g < TX / 2) { lty = -1; ltx = 2 * g + 1; }
             else if (g < TX) { lty = TY; ltx = 2 * (g - TX / 2); }
             else if (g < TX + TY / 2) { ltx = -1; lty = 2 * (g - TX) + 1; }
@@ -221,63 +287,60 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         int gtx = bx * TX + ltx, gty = by * TY + lty;
         gtx = gtx < 0 ? gtx + T : (gtx >= T ? gtx - T : gtx);
         gty = gty < 0 ? gty + T : (gty >= T ? gty - T : gty);
-        const int base = (lty * D + RING) * RW + ltx * D + RING;
-        const int a = tile_attempts<D, RW>(lds, base, (uint32_t)(gty * T + gtx), s, 0u, N, k0, k1);
-        if (k < HALF) acc += a;
+        const int base = (lty * D + G::RING) * G::RWL + ltx * D + off;
+        const int a = tile_attempts<D, G::RWL, E>(lds, base, (uint32_t)(gty * T + gtx), s, 0u,
+                                                  N, k0, k1);
+        if (k < G::HALF) acc += a;
     }
     __syncthreads();
     // phase 1: colour-1 tiles of the block
-    for (int k = threadIdx.x; k < HALF; k += NT) {
+    for (int k = threadIdx.x; k < G::HALF; k += NT) {
         const int lty = k / (TX / 2);
         const int ltx = 2 * (k % (TX / 2)) + 1 - (lty & 1);
         const int gtx = bx * TX + ltx, gty = by * TY + lty;
-        const int base = (lty * D + RING) * RW + ltx * D + RING;
-        acc += tile_attempts<D, RW>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1);
+        const int base = (lty * D + G::RING) * G::RWL + ltx * D + off;
+        acc += tile_attempts<D, G::RWL, E>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1);
     }
     __syncthreads();
 
     // store the block and reduce its sums
     long long s1 = 0, s2 = 0;
-    constexpr int BW = TX * D, BH = TY * D;
-    for (int i = threadIdx.x; i < BW * BH; i += NT) {
-        const int r = i / BW, c = i - r * BW;
-        const int v = lds[(r + RING) * RW + c + RING];
-        int gy = gy0 + RING + r; if (gy >= L) gy -= L;
-        int gx = gx0 + RING + c; if (gx >= L) gx -= L;
+    for (int i = threadIdx.x; i < G::BW * G::BH; i += NT) {
+        const int r = i / G::BW, c = i - r * G::BW;
+        const int v = ref + (int)lds[(r + G::RING) * G::RWL + c + off];
+        int gy = gy0 + G::RING + r; if (gy >= L) gy -= L;
+        int gx = gx0 + G::RING + c; if (gx >= L) gx -= L;
         hout[(size_t)gy * L + gx] = v;
         s1 += v;
         s2 += (long long)v * v;
     }
     block_reduce3<NT>(s1, s2, acc);
     if (threadIdx.x == 0) {
-        long long *p = partials + 3 * (d.part_start + b);
-        p[0] = s1;
-        p[1] = s2;
-        p[2] = acc;
+        unsigned long long *a = reinterpret_cast<unsigned long long *>(d.acc + 3 * (b & (kAccSlots - 1)));
+        atomicAdd(a + 0, (unsigned long long)s1);
+        atomicAdd(a + 1, (unsigned long long)s2);
+        atomicAdd(a + 2, (unsigned long long)acc);
     }
 }
 
-// Sums each active surface's partials into its log and advances t.
-template <int NT>
-__global__ __launch_bounds__(NT) void reduce_partials(SurfDev *__restrict__ descs,
-                                                      const long long *__restrict__ partials)
+// Folds each active surface's accumulators into its log, clears them and
+// advances t.  One 64-thread workgroup per surface.
+__global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs)
 {
     SurfDev &d = descs[blockIdx.x];
     const long long t = d.t;
     if (t >= d.t_end) return;
-    long long a = 0, b = 0, c = 0;
-    const long long *p = partials + 3 * d.part_start;
-    for (int i = threadIdx.x; i < d.nblocks; i += NT) {
-        a += p[3 * i];
-        b += p[3 * i + 1];
-        c += p[3 * i + 2];
-    }
-    block_reduce3<NT>(a, b, c);
+    long long *a = d.acc + 3 * threadIdx.x;
+    long long x = a[0], y = a[1], z = a[2];
+    a[0] = 0;
+    a[1] = 0;
+    a[2] = 0;
+    wave_reduce3(x, y, z);
     if (threadIdx.x == 0) {
         long long *e = d.log + 3 * ((t + 1) % d.log_cap);
-        e[0] = a;
-        e[1] = b;
-        e[2] = c;
+        e[0] = x;
+        e[1] = y;
+        e[2] = z;
         d.t = t + 1;
     }
 }

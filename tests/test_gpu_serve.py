@@ -1,0 +1,105 @@
+"""GPU tests of the continuous-batching engine.
+
+Each job's trajectory is a function of its own (L, N, D, seed) only, so
+every result must equal, bit for bit, the same job run alone (and the CPU
+oracle), whatever else shared the device, whenever it was admitted, and
+whichever jobs were cancelled around it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[serve] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1605_02620_amd as p
+    from paper_1605_02620_amd import serve
+    return p, serve
+
+
+JOBS = [  # L, N, seed, t_max
+    (256, 1, 11, 40), (64, 2, 12, 70), (512, 4, 13, 25), (128, 1, 14, 33),
+    (256, 2, 15, 17), (1024, 1, 16, 12), (64, 1, 17, 5), (384, 1, 18, 29),
+    (256, 4, 19, 50), (128, 2, 20, 3), (512, 1, 21, 19), (64, 4, 22, 44),
+]
+
+
+def test_mix_equals_alone_and_oracle(pkg, oracle):
+    rsos, serve = pkg
+    # a pool that holds only a few jobs at a time forces queueing and reuse
+    eng = serve.Engine(pool_bytes=16 << 20, max_running=4, D=8)
+    ids = []
+    for (L, N, seed, tm) in JOBS:
+        grid = sorted(set(workloads.pow2_grid(tm)))
+        ids.append(eng.submit(L, N, seed, tm, grid, keep_heights=True))
+    _say(f"submitted {len(ids)} jobs")
+    for _ in range(1000):
+        eng.step(16)
+        if eng.stats()["finished"] == len(JOBS):
+            break
+    assert eng.stats()["finished"] == len(JOBS)
+    for jid, (L, N, seed, tm) in zip(ids, JOBS):
+        _say(f"job L={L} N={N} seed={seed} t_max={tm}")
+        samples, h, lat = eng.result(jid, heights=True)
+        alone = rsos.Surface(L, N=N, seed=seed, D=8)
+        alone.sweep(tm)
+        assert np.array_equal(h, alone.heights())
+        ref_h = workloads.flat(L)
+        r_log = oracle.run(ref_h, L, N, 8, seed=seed, t0=0, n=tm)
+        assert np.array_equal(h, ref_h)
+        for rec in samples:
+            t = int(rec["t"])
+            assert (rec["s1"], rec["s2"], rec["accepted"]) == tuple(int(x) for x in r_log[t - 1, 1:])
+        assert lat > 0
+        eng.release(jid)
+    eng.close()
+
+
+def test_cancel_leaves_others_unchanged(pkg, oracle):
+    rsos, serve = pkg
+    eng = serve.Engine(pool_bytes=32 << 20, max_running=8, D=8)
+    keep = [(256, 1, 31, 30), (128, 2, 32, 30), (512, 1, 33, 20)]
+    drop = [(256, 4, 34, 1000), (64, 1, 35, 1000)]
+    kid = [eng.submit(L, N, s, tm, [tm], keep_heights=True) for (L, N, s, tm) in keep]
+    did = [eng.submit(L, N, s, tm, [tm]) for (L, N, s, tm) in drop]
+    eng.step(16)
+    for d in did:
+        eng.cancel(d)
+    for _ in range(100):
+        eng.step(16)
+        if eng.stats()["running"] == 0 and eng.stats()["queued"] == 0:
+            break
+    for d in did:
+        assert eng.poll(d)[0] == serve.JOB_CANCELLED
+    for jid, (L, N, s, tm) in zip(kid, keep):
+        _, h, _ = eng.result(jid, heights=True)
+        ref_h = workloads.flat(L)
+        oracle.run(ref_h, L, N, 8, seed=s, t0=0, n=tm)
+        assert np.array_equal(h, ref_h)
+    assert eng.stats()["bytes_in_use"] == 0
+    eng.close()
+
+
+def test_poisson_stream_summary(pkg):
+    """A short real-time stream: latencies are reported and every job ends."""
+    rsos, serve = pkg
+    jobs = workloads.job_stream(n_jobs=40, rate_per_s=200.0, seed=5, L_pow=(7, 10),
+                                t_range=(10, 200))
+    eng = serve.Engine(pool_bytes=256 << 20, max_running=64, D=8)
+    res, summ = serve.serve(eng, jobs)
+    _say(f"summary {summ}")
+    assert summ["jobs_done"] == len(jobs)
+    assert 0 < summ["latency_p50_s"] <= summ["latency_p99_s"]
+    eng.close()
