@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -165,6 +167,17 @@ def main():
                       "L": L, "N": N, "D": D, "seed": seed, "sweeps": args.steps,
                       "final_t": int(w["t"]), "final_w2": float(w["w2"])},
            "roofline": roofline}
+    if args.copy_probe:
+        src = torch.ones(L * L, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe"] = {"bytes_each": 2 * src.numel() * 4, "copies": 5,
+                             "GBps": round(5 * 2 * src.numel() * 4 / (time.perf_counter() - t0) / 1e9, 1)}
+        del src, dst
     if not args.no_batch:
         out["batched"] = bench_batched()
     if not args.no_cpu:

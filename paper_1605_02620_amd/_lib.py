@@ -13,7 +13,9 @@ import os
 import torch  # noqa: F401  (HIP runtime shared with the library)
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-SO_PATH = os.path.join(_PKG, "librsos.so")
+# RSOS_LIBRARY selects another build of the same library (e.g. to compare
+# compile-time variants); by default the in-tree build is used.
+SO_PATH = os.environ.get("RSOS_LIBRARY") or os.path.join(_PKG, "librsos.so")
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 c_vp = ctypes.c_void_p

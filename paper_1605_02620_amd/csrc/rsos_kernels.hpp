@@ -33,6 +33,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rsosk {
 
 // ---------------------------------------------------------------------------
@@ -115,20 +117,22 @@ struct BlockGeom {
 // D^2 sequential attempts of one tile whose site (u, v) sits at LDS index
 // base + v*P + u (neighbours at +-1 and +-P).  E is the LDS element type:
 // int16 holds heights relative to a per-block reference, int32 raw heights.
-// Returns the accepted count.
-template <int D, int P, typename E>
-__device__ __forceinline__ int tile_attempts(E *lds, int base, uint32_t tile_id, uint32_t s,
-                                             uint32_t p, int N, uint32_t k0, uint32_t k1)
+// Adds the accepted count to acc and, over accepted attempts, 2c + 1 (c the
+// staged value before the deposit) to q: a deposit on height h raises
+// sum h^2 by 2h + 1.
+template <int D, int P, typename E, typename Q>
+__device__ __forceinline__ void tile_attempts(E *lds, int base, uint32_t tile_id, uint32_t s,
+                                              uint32_t p, int N, uint32_t k0, uint32_t k1,
+                                              int &acc, Q &q)
 {
     using TB = TileBits<D>;
-    int acc = 0;
 #pragma unroll 1
     for (int j = 0; j < TB::NCALL; ++j) {
         const u32x4 r = philox4x32_10((uint32_t)j, tile_id, s, p, k0, k1);
 #pragma unroll
-        for (int q = 0; q < TB::PER; ++q) {
-            if (j * TB::PER + q < D * D) {
-                const uint32_t f = (r.v[q / TB::F] >> ((q % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
+        for (int k = 0; k < TB::PER; ++k) {
+            if (j * TB::PER + k < D * D) {
+                const uint32_t f = (r.v[k / TB::F] >> ((k % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
                 const int idx = base + (int)(f >> TB::LOG2D) * P + (int)(f & (D - 1));
                 const int c = lds[idx];
                 const int m = min(min((int)lds[idx - 1], (int)lds[idx + 1]),
@@ -138,10 +142,10 @@ __device__ __forceinline__ int tile_attempts(E *lds, int base, uint32_t tile_id,
                 const int ok = (c - m) < N;
                 lds[idx] = (E)(c + ok);
                 acc += ok;
+                q += ok ? (Q)2 * (Q)c + (Q)1 : (Q)0;
             }
         }
     }
-    return acc;
 }
 
 // XCD-aware renumbering: the dispatcher hands consecutive workgroup ids to
@@ -197,6 +201,24 @@ __device__ __forceinline__ void lds_put4<int32_t>(int32_t *dst, const int4 v, in
     *reinterpret_cast<int4 *>(dst) = v;
 }
 
+template <typename E> struct Lds4;
+template <> struct Lds4<int16_t> {
+    typedef uint2 raw;
+    __device__ static int4 widen(const uint2 w, int ref)
+    {
+        return make_int4(ref + (int)(int16_t)(w.x & 0xFFFF), ref + (int)(int16_t)(w.x >> 16),
+                         ref + (int)(int16_t)(w.y & 0xFFFF), ref + (int)(int16_t)(w.y >> 16));
+    }
+};
+template <> struct Lds4<int32_t> {
+    typedef int4 raw;
+    __device__ static int4 widen(const int4 w, int) { return w; }
+};
+
+
+
+
+
 // ---------------------------------------------------------------------------
 // block_sweep: one sweep for every active surface of the descriptor table.
 // Requirements checked on the host: T % TX == 0, T % TY == 0, TX and TY
@@ -205,11 +227,16 @@ __device__ __forceinline__ void lds_put4<int32_t>(int32_t *dst, const int4 v, in
 // of the reference: any two region sites are joined by a path of at most
 // RW + RH - 2 bonds, each of height difference <= N, and no site gains
 // more than D^2 in a sweep).
+// The block's accumulator slot receives (A, 2 ref A + sum(2c+1), A): the
+// sweep's increments of S1 and S2 (exact), from which reduce_acc advances
+// the surface's sums.
 // ---------------------------------------------------------------------------
 template <int D, int TX, int TY, int NT, typename E>
 __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf)
 {
     using G = BlockGeom<D, TX, TY>;
+    using Q = typename std::conditional<sizeof(E) == 2, int, long long>::type;
+    constexpr int NW = NT / 64;
     __shared__ __attribute__((aligned(16))) E lds[G::RWL * G::RH];
 
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -239,39 +266,46 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     if (gx0 < 0) gx0 += L;
     if (gy0 < 0) gy0 += L;
     const int cpad = gx0 & 3;
-    const int gxa = gx0 - cpad;
+    const int gxa = gx0 - cpad;  // LDS column c holds global column gxa + c (mod L)
     const int ref = (sizeof(E) == 2) ? hin[(size_t)gy0 * L + gx0] : 0;
 
-    // load the region in aligned 16-byte chunks, U chunks in flight per thread
-    constexpr int NCH = G::CH * G::RH;
-    constexpr int U = 8;
-    for (int i0 = threadIdx.x; i0 < NCH; i0 += NT * U) {
-        int4 v[U];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // ---- load the region in aligned 16-byte chunks, consecutive threads on
+    // consecutive chunks (rows run on into the next), U chunks in flight
+    {
+        constexpr int NCH = G::CH * G::RH;
+        constexpr int U = 8;
+        for (int i0 = threadIdx.x; i0 < NCH; i0 += NT * U) {
+            int4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * NT;
-            if (i < NCH) {
-                const int r = i / G::CH, cc = i - r * G::CH;
-                int gy = gy0 + r; if (gy >= L) gy -= L;
-                int gx = gxa + 4 * cc; if (gx >= L) gx -= L;
-                v[u] = *reinterpret_cast<const int4 *>(hin + (size_t)gy * L + gx);
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * NT;
+                if (i < NCH) {
+                    const int r = i / G::CH, cc = i - r * G::CH;
+                    int gy = gy0 + r; if (gy >= L) gy -= L;
+                    int gx = gxa + 4 * cc; if (gx >= L) gx -= L;
+                    v[u] = *reinterpret_cast<const int4 *>(hin + (size_t)gy * L + gx);
+                }
             }
-        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * NT;
-            if (i < NCH) {
-                const int r = i / G::CH, cc = i - r * G::CH;
-                lds_put4<E>(lds + r * G::RWL + 4 * cc, v[u], ref);
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * NT;
+                if (i < NCH) {
+                    const int r = i / G::CH, cc = i - r * G::CH;
+                    lds_put4<E>(lds + r * G::RWL + 4 * cc, v[u], ref);
+                }
             }
         }
     }
     __syncthreads();
 
-    const int off = G::RING + cpad;  // LDS column of block column 0 is off + ...
-    long long acc = 0;
-    // phase 0: colour-0 tiles of the block, then the colour-0 ring tiles that
-    // touch the block's colour-1 border tiles
+    const int off = G::RING + cpad;  // LDS column of block column 0
+    int acc = 0;
+    Q q = 0;
+    // ---- phase 0: colour-0 tiles of the block, then the colour-0 ring tiles
+    // that touch the block's colour-1 border tiles (their counts are the
+    // neighbouring blocks' and are dropped here)
     for (int k = threadIdx.x; k < G::P0; k += NT) {
         int ltx, lty;
         if (k < G::HALF) {
@@ -288,42 +322,77 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         gtx = gtx < 0 ? gtx + T : (gtx >= T ? gtx - T : gtx);
         gty = gty < 0 ? gty + T : (gty >= T ? gty - T : gty);
         const int base = (lty * D + G::RING) * G::RWL + ltx * D + off;
-        const int a = tile_attempts<D, G::RWL, E>(lds, base, (uint32_t)(gty * T + gtx), s, 0u,
-                                                  N, k0, k1);
-        if (k < G::HALF) acc += a;
+        int a = 0;
+        Q qq = 0;
+        tile_attempts<D, G::RWL, E, Q>(lds, base, (uint32_t)(gty * T + gtx), s, 0u, N, k0, k1, a, qq);
+        if (k < G::HALF) { acc += a; q += qq; }
     }
     __syncthreads();
-    // phase 1: colour-1 tiles of the block
+    // ---- phase 1: colour-1 tiles of the block
     for (int k = threadIdx.x; k < G::HALF; k += NT) {
         const int lty = k / (TX / 2);
         const int ltx = 2 * (k % (TX / 2)) + 1 - (lty & 1);
         const int gtx = bx * TX + ltx, gty = by * TY + lty;
         const int base = (lty * D + G::RING) * G::RWL + ltx * D + off;
-        acc += tile_attempts<D, G::RWL, E>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1);
+        tile_attempts<D, G::RWL, E, Q>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1, acc, q);
     }
     __syncthreads();
 
-    // store the block and reduce its sums
-    long long s1 = 0, s2 = 0;
-    for (int i = threadIdx.x; i < G::BW * G::BH; i += NT) {
-        const int r = i / G::BW, c = i - r * G::BW;
-        const int v = ref + (int)lds[(r + G::RING) * G::RWL + c + off];
-        int gy = gy0 + G::RING + r; if (gy >= L) gy -= L;
-        int gx = gx0 + G::RING + c; if (gx >= L) gx -= L;
-        hout[(size_t)gy * L + gx] = v;
-        s1 += v;
-        s2 += (long long)v * v;
+    // ---- store the block: aligned 16-byte chunks (LDS and global columns
+    // share their alignment), masked single stores in the partial chunks
+    {
+        constexpr int SPR = G::BW / 4;  // chunk slots per row starting at the first partial one
+        static_assert(SPR <= 64 && 64 % SPR == 0, "block width must tile a wavefront");
+        constexpr int RPW = 64 / SPR;   // rows per wave pass
+        const int m = off & 3;
+        const int kslot = (off >> 2) + lane % SPR;  // LDS chunk index of this lane
+        int gc = gxa + 4 * kslot;
+        if (gc >= L) gc -= L;
+        const bool partial = (lane % SPR == 0) && m != 0;
+        for (int r = wave * RPW + lane / SPR; r < G::BH; r += NW * RPW) {
+            int gy = gy0 + G::RING + r;
+            if (gy >= L) gy -= L;
+            int32_t *row = hout + (size_t)gy * L;
+            const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
+            const int4 v = Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref);
+            if (!partial) {
+                *reinterpret_cast<int4 *>(row + gc) = v;
+            } else {
+                if (m <= 1) row[gc + 1] = v.y;
+                if (m <= 2) row[gc + 2] = v.z;
+                row[gc + 3] = v.w;
+            }
+        }
+        // the trailing partial chunk of each row (cells 0 .. m-1)
+        if (m != 0) {
+            const int kt = (off >> 2) + SPR;
+            int gct = gxa + 4 * kt;
+            if (gct >= L) gct -= L;
+            for (int r = threadIdx.x; r < G::BH; r += NT) {
+                int gy = gy0 + G::RING + r;
+                if (gy >= L) gy -= L;
+                int32_t *row = hout + (size_t)gy * L;
+                const E *src = lds + (G::RING + r) * G::RWL + 4 * kt;
+                row[gct] = ref + (int)src[0];
+                if (m >= 2) row[gct + 1] = ref + (int)src[1];
+                if (m >= 3) row[gct + 2] = ref + (int)src[2];
+            }
+        }
     }
-    block_reduce3<NT>(s1, s2, acc);
+
+    long long A = acc, S2inc = (long long)q, unused = 0;
+    block_reduce3<NT>(A, S2inc, unused);
     if (threadIdx.x == 0) {
+        S2inc += 2ll * ref * A;
         unsigned long long *a = reinterpret_cast<unsigned long long *>(d.acc + 3 * (b & (kAccSlots - 1)));
-        atomicAdd(a + 0, (unsigned long long)s1);
-        atomicAdd(a + 1, (unsigned long long)s2);
-        atomicAdd(a + 2, (unsigned long long)acc);
+        atomicAdd(a + 0, (unsigned long long)A);
+        atomicAdd(a + 1, (unsigned long long)S2inc);
+        atomicAdd(a + 2, (unsigned long long)A);
     }
 }
 
-// Folds each active surface's accumulators into its log, clears them and
+// Folds each active surface's accumulated increments into its log (the
+// record of t+1 is the record of t plus the increments), clears them and
 // advances t.  One 64-thread workgroup per surface.
 __global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs)
 {
@@ -337,9 +406,11 @@ __global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs)
     a[2] = 0;
     wave_reduce3(x, y, z);
     if (threadIdx.x == 0) {
+        const long long *prev = d.log + 3 * (t % d.log_cap);
         long long *e = d.log + 3 * ((t + 1) % d.log_cap);
-        e[0] = x;
-        e[1] = y;
+        const long long s1 = prev[0] + x, s2 = prev[1] + y;
+        e[0] = s1;
+        e[1] = s2;
         e[2] = z;
         d.t = t + 1;
     }
