@@ -149,13 +149,23 @@ def main():
     launches, mean_ms, _ = s.timing_read()
     s.timing(False)
     w = s.width()
+    kname = s.kernel_name()
     s.close()
     achieved = L * L * BYTES_PER_ATTEMPT / (mean_ms * 1e-3) / 1e9
+    # measured HBM bytes per launch from the committed counter summary, only
+    # while it describes this kernel source and instance
+    from paper_1605_02620_amd import profiling
+    tr = profiling.current_traffic(os.path.join(ROOT, "profiles", "block_sweep_traffic.json"))
+    traffic = None
+    rk = (tr or {}).get("kernel", "").replace(" ", "")
+    rk = rk.replace(",signedchar,", ",int8,").replace(",short,", ",int16,").replace(",int,", ",int32,")
+    if tr is not None and rk.startswith("voidrsosk::" + kname[:-1] + ","):
+        traffic = tr["traffic_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "block_sweep<8,16,8,64>", "launches_timed": launches,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch", "kernel": kname, "launches_timed": launches,
                 "kernel_mean_ms": round(mean_ms, 4),
-                "bytes_per_launch": L * L * BYTES_PER_ATTEMPT}
+                "algorithmic_bytes_per_launch": L * L * BYTES_PER_ATTEMPT}
 
     out = {"metric": "attempted site updates/ns", "value": round(value, 3),
            "unit": "attempts/ns", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -139,6 +139,12 @@ rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current);
 rsos_status rsos_timing(rsos_surface *s, int enable);
 rsos_status rsos_timing_read(rsos_surface *s, int64_t *launches, double *mean_ms, double *total_ms);
 
+/* Name of the tile-block kernel instance that sweeps this surface, e.g.
+ * "block_sweep<8,16,8,128,int16>" (D, tiles per block in x and y, threads,
+ * LDS element type), or "lds_run<8>" for an LDS-resident surface; written
+ * NUL-terminated into buf (at most len bytes). */
+rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len);
+
 /* Frees the handle and library-owned memory (never d_h, never a
  * caller-provided d_work).  Synchronises the stream first. */
 rsos_status rsos_free(rsos_surface *s);

@@ -49,6 +49,7 @@ SIGNATURES = [
     ("rsos_time", c_i32, [c_vp, P(c_i64), P(c_vp)]),
     ("rsos_timing", c_i32, [c_vp, ctypes.c_int]),
     ("rsos_timing_read", c_i32, [c_vp, P(c_i64), P(ctypes.c_double), P(ctypes.c_double)]),
+    ("rsos_kernel_name", c_i32, [c_vp, ctypes.c_char_p, c_i32]),
     ("rsos_free", c_i32, [c_vp]),
     ("rsos_batch_init", c_i32, [P(c_vp), c_i32, P(Params), c_vp, c_vp, P(c_i64), c_i64, c_vp]),
     ("rsos_batch_sweep", c_i32, [c_vp, P(c_i64), c_i64]),

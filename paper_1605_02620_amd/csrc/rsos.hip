@@ -45,33 +45,48 @@ rsos_status fail(rsos_status st, const char *fmt, ...)
 
 constexpr int kLdsMaxBytes = 64 * 1024;  // lds_run: whole surface in LDS
 constexpr int kGraphSweeps = 32;
+constexpr int kFallbackGrid = 256;  // workgroups walking the fallback queue
 
 // ---------------------------------------------------------------------------
 // Block-kernel variants.  The tile block shape never changes results; it
 // only has to tile the lattice: T % TX == 0, T % TY == 0, region <= L.
 // ---------------------------------------------------------------------------
-typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int);
+typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int, int *);
 
-template <int D, int TX, int TY, int NT, typename E>
-void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n)
+template <int D, int TX, int TY, int NT, typename E, bool FB>
+void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E>), grid, dim3(NT), 0, st, d, n);
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, queue);
 }
 
 struct Variant {
-    int D, TX, TY, NT, elem;  // elem: LDS bytes per site (2 = int16 offsets, 4 = int32)
+    int D, TX, TY, NT, elem;  // elem: LDS bytes per site (1 and 2: offsets from a block reference)
     BlockLaunch launch;
+    BlockLaunch fallback;     // for elem == 1: the same blocks with wider staging
+    int fb_elem;
 };
 
-#define V16(D, TX, TY, NT) {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t>}
-#define V32(D, TX, TY, NT) {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t>}
+// int8 staging checks every block's range and queues the few that do not
+// fit for a second launch of the same block shape with int16 (or int32)
+// staging.
+#define V8(D, TX, TY, NT)                                                                     \
+    {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
+     launch_block<D, TX, TY, NT, int16_t, true>, 2}
+#define V8W(D, TX, TY, NT)                                                                    \
+    {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
+     launch_block<D, TX, TY, NT, int32_t, true>, 4}
+#define V16(D, TX, TY, NT) {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0}
+#define V32(D, TX, TY, NT) {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, false>, nullptr, 0}
 // In order of preference; the first one that fits every surface is used.
 const Variant kVariants[] = {
     V16(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
     V16(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64),
-    V16(8, 16, 8, 128), V16(8, 16, 16, 192), V16(8, 32, 8, 192), V16(8, 8, 8, 64), V32(8, 16, 8, 128), V32(8, 8, 8, 64), V32(8, 2, 2, 64),
+    V8(8, 32, 8, 192), V8W(8, 32, 8, 192), V16(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
+    V32(8, 8, 8, 64), V32(8, 2, 2, 64),
     V16(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
 };
+#undef V8
+#undef V8W
 #undef V16
 #undef V32
 
@@ -82,7 +97,11 @@ bool variant_fits(const Variant &v, int L, int N)
     const int rwl = (rw + 6) & ~3;
     if (T % v.TX != 0 || T % v.TY != 0 || rwl > L || rh > L) return false;
     // int16 staging: every staged value within 32767 of the block reference
-    if (v.elem == 2 && (long long)N * (rw + rh + 4) + v.D * v.D > 32767) return false;
+    const bool i16_ok = (long long)N * (rw + rh + 4) + v.D * v.D <= 32767;
+    if (v.elem == 2 && !i16_ok) return false;
+    // int8 staging: the sweep's growth N D must leave room in the byte; the
+    // fallback's wider type must hold the blocks that still do not fit
+    if (v.elem == 1 && ((long long)N * v.D > 96 || (v.fb_elem == 2 && !i16_ok))) return false;
     return true;
 }
 
@@ -95,7 +114,7 @@ const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN)
         if (v.D != D) continue;
         if (force) {
             char want[48];
-            snprintf(want, sizeof want, "%dx%dx%dx%d", v.TX, v.TY, v.NT, v.elem);
+            snprintf(want, sizeof want, "%dx%dx%dx%d", v.TX, v.TY, v.NT, v.elem);  // e.g. 32x8x192x1
             if (strcmp(force, want) != 0) continue;
         }
         bool ok = true;
@@ -233,6 +252,7 @@ struct SurfaceGroup {
     std::vector<long long> max_h0, t0; // per surface
     SurfDev *d_desc = nullptr;
     long long *d_acc = nullptr;        // kAccSlots x 3 accumulators per block-path surface
+    int *d_queue = nullptr;            // blocks handed to the wider fallback launch
     std::vector<int> lds_idx, blk_idx; // surfaces on each path
     int *d_lds_idx = nullptr;
     const Variant *variant = nullptr;
@@ -295,6 +315,9 @@ struct SurfaceGroup {
             HIP_TRY(hipMemset(d_acc, 0, bytes));
             for (size_t k = 0; k < blk_idx.size(); ++k)
                 host[blk_idx[k]].acc = d_acc + 3 * rsosk::kAccSlots * k;
+            if ((st = dev_alloc((void **)&d_queue, sizeof(int) * (1 + (size_t)total_blocks))) != RSOS_OK)
+                return st;
+            HIP_TRY(hipMemset(d_queue, 0, sizeof(int)));
         }
         if (!lds_idx.empty()) {
             if ((st = dev_alloc((void **)&d_lds_idx, sizeof(int) * lds_idx.size())) != RSOS_OK) return st;
@@ -365,6 +388,17 @@ struct SurfaceGroup {
         return RSOS_OK;
     }
 
+    // the tile-block sweep proper: one workgroup per block, then (int8
+    // staging) the queued blocks with wider staging
+    void launch_block_sweep()
+    {
+        const int n = (int)blk_idx.size();
+        variant->launch(dim3(total_blocks), stream, d_desc, n, d_queue);
+        if (variant->fallback)
+            variant->fallback(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n,
+                              d_queue);
+    }
+
     rsos_status enqueue_one()
     {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -374,11 +408,11 @@ struct SurfaceGroup {
             timed.push_back({e0, e1});
             HIP_TRY(hipEventRecord(e0, stream));
         }
-        variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size());
+        launch_block_sweep();
         HIP_TRY(hipGetLastError());
         if (timing) HIP_TRY(hipEventRecord(e1, stream));
         hipLaunchKernelGGL(rsosk::reduce_acc, dim3((unsigned)blk_idx.size()), dim3(64), 0, stream,
-                           d_desc);
+                           d_desc, d_queue);
         HIP_TRY(hipGetLastError());
         return RSOS_OK;
     }
@@ -388,9 +422,9 @@ struct SurfaceGroup {
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < k; ++i) {
-            variant->launch(dim3(total_blocks), stream, d_desc, (int)blk_idx.size());
+            launch_block_sweep();
             hipLaunchKernelGGL(rsosk::reduce_acc, dim3((unsigned)blk_idx.size()), dim3(64), 0,
-                               stream, d_desc);
+                               stream, d_desc, d_queue);
         }
         HIP_TRY(hipStreamEndCapture(stream, &g));
         HIP_TRY(hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));
@@ -645,6 +679,20 @@ rsos_status rsos_timing_read(rsos_surface *s, int64_t *launches, double *mean_ms
 {
     CHECK_HANDLE(s, s->g);
     return mark(s->g, s->g.read_timing(launches, mean_ms, total_ms));
+}
+
+rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len)
+{
+    CHECK_HANDLE(s, s->g);
+    if (!buf || len < 1) return fail(RSOS_E_INVAL, "bad buffer");
+    const SurfaceGroup &g = s->g;
+    if (g.variant)
+        snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s>", g.variant->D, g.variant->TX,
+                 g.variant->TY, g.variant->NT,
+                 g.variant->elem == 1 ? "int8" : g.variant->elem == 2 ? "int16" : "int32");
+    else
+        snprintf(buf, (size_t)len, "lds_run<%d>", g.D);
+    return RSOS_OK;
 }
 
 rsos_status rsos_free(rsos_surface *s)

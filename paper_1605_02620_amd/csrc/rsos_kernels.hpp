@@ -89,6 +89,10 @@ struct SurfDev {
     int block_start;      // first global block index of this surface
 };
 
+// Blocks whose staged heights would not fit the narrow LDS element type are
+// handed to a second launch with a wider type: queue[0] counts them, queue[1..]
+// lists their global block indices.  reduce_acc clears the count.
+
 template <int D>
 struct TileBits {
     static constexpr int LOG2D = (D == 2) ? 1 : (D == 4) ? 2 : (D == 8) ? 3 : (D == 16) ? 4 : 5;
@@ -196,6 +200,14 @@ __device__ __forceinline__ void lds_put4<int16_t>(int16_t *dst, const int4 v, in
 }
 
 template <>
+__device__ __forceinline__ void lds_put4<int8_t>(int8_t *dst, const int4 v, int ref)
+{
+    const uint32_t w = (uint32_t)(uint8_t)(v.x - ref) | ((uint32_t)(uint8_t)(v.y - ref) << 8) |
+                       ((uint32_t)(uint8_t)(v.z - ref) << 16) | ((uint32_t)(uint8_t)(v.w - ref) << 24);
+    *reinterpret_cast<uint32_t *>(dst) = w;
+}
+
+template <>
 __device__ __forceinline__ void lds_put4<int32_t>(int32_t *dst, const int4 v, int)
 {
     *reinterpret_cast<int4 *>(dst) = v;
@@ -210,6 +222,14 @@ template <> struct Lds4<int16_t> {
                          ref + (int)(int16_t)(w.y & 0xFFFF), ref + (int)(int16_t)(w.y >> 16));
     }
 };
+template <> struct Lds4<int8_t> {
+    typedef uint32_t raw;
+    __device__ static int4 widen(const uint32_t w, int ref)
+    {
+        return make_int4(ref + (int)(int8_t)(w & 0xFF), ref + (int)(int8_t)((w >> 8) & 0xFF),
+                         ref + (int)(int8_t)((w >> 16) & 0xFF), ref + (int)(int8_t)(w >> 24));
+    }
+};
 template <> struct Lds4<int32_t> {
     typedef int4 raw;
     __device__ static int4 widen(const int4 w, int) { return w; }
@@ -218,6 +238,15 @@ template <> struct Lds4<int32_t> {
 
 
 
+
+// The next sweep reads the output from HBM long after this one wrote it:
+// stream the full 16-byte chunks past the caches.
+__device__ __forceinline__ void store4_stream(int32_t *dst, const int4 v)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(dst));
+}
 
 // ---------------------------------------------------------------------------
 // block_sweep: one sweep for every active surface of the descriptor table.
@@ -231,15 +260,34 @@ template <> struct Lds4<int32_t> {
 // sweep's increments of S1 and S2 (exact), from which reduce_acc advances
 // the surface's sums.
 // ---------------------------------------------------------------------------
-template <int D, int TX, int TY, int NT, typename E>
-__global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf)
+template <typename E>
+struct StageLimits {
+    // staged values are kept as E relative to the block reference; int8
+    // blocks check their range at load time, wider types are chosen by the
+    // host so that every value fits
+    static constexpr bool checked = sizeof(E) == 1;
+};
+
+// FALLBACK = false: every workgroup takes one block (grid = all blocks of
+// the table); an int8 workgroup whose block does not fit queues it and
+// stops.  FALLBACK = true: workgroups walk the queue of the preceding
+// int8 launch.
+template <int D, int TX, int TY, int NT, typename E, bool FALLBACK>
+__global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf,
+                                                  int *__restrict__ queue)
 {
     using G = BlockGeom<D, TX, TY>;
-    using Q = typename std::conditional<sizeof(E) == 2, int, long long>::type;
-    constexpr int NW = NT / 64;
+    using Q = typename std::conditional<sizeof(E) <= 2, int, long long>::type;
     __shared__ __attribute__((aligned(16))) E lds[G::RWL * G::RH];
+    __shared__ int s_bad;
 
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (StageLimits<E>::checked) {
+        if (threadIdx.x == 0) s_bad = 0;
+        __syncthreads();
+    }
+    const int nq = FALLBACK ? queue[0] : 1;
+    for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
+    const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
     int lo = 0, hi = nsurf - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -247,7 +295,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     }
     const SurfDev &d = descs[lo];
     const long long t = d.t;
-    if (t >= d.t_end) return;
+    if (t >= d.t_end) continue;
 
     const int L = d.L, N = d.N, T = d.T;
     const uint32_t s = (uint32_t)t;
@@ -267,10 +315,9 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     if (gy0 < 0) gy0 += L;
     const int cpad = gx0 & 3;
     const int gxa = gx0 - cpad;  // LDS column c holds global column gxa + c (mod L)
-    const int ref = (sizeof(E) == 2) ? hin[(size_t)gy0 * L + gx0] : 0;
+    const int ref = (sizeof(E) <= 2) ? hin[(size_t)gy0 * L + gx0] : 0;
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
+    int vmin = 0x7FFFFFFF, vmax = -0x7FFFFFFF;  // range of the staged heights (int8 staging)
     // ---- load the region in aligned 16-byte chunks, consecutive threads on
     // consecutive chunks (rows run on into the next), U chunks in flight
     {
@@ -294,11 +341,29 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
                 if (i < NCH) {
                     const int r = i / G::CH, cc = i - r * G::CH;
                     lds_put4<E>(lds + r * G::RWL + 4 * cc, v[u], ref);
+                    if (StageLimits<E>::checked) {
+                        vmin = min(vmin, min(min(v[u].x, v[u].y), min(v[u].z, v[u].w)));
+                        vmax = max(vmax, max(max(v[u].x, v[u].y), max(v[u].z, v[u].w)));
+                    }
                 }
             }
         }
     }
+    if (StageLimits<E>::checked) {
+        // every value of the sweep stays in [min, max + N D]: heights never
+        // decrease, and a tile site is never more than N D/2 above the
+        // frozen sites around its tile (a path of at most D/2 bonds), whose
+        // values grow by at most N D/2 in the first phase
+        if (vmin - ref < -128 || (long long)vmax - ref + (long long)N * D > 127) s_bad = 1;
+    }
     __syncthreads();
+    if (StageLimits<E>::checked && s_bad) {
+        if (threadIdx.x == 0) {
+            const int k = atomicAdd(queue, 1);
+            queue[1 + k] = lb;
+        }
+        continue;  // uniform: the whole workgroup leaves this block
+    }
 
     const int off = G::RING + cpad;  // LDS column of block column 0
     int acc = 0;
@@ -341,22 +406,23 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     // ---- store the block: aligned 16-byte chunks (LDS and global columns
     // share their alignment), masked single stores in the partial chunks
     {
-        constexpr int SPR = G::BW / 4;  // chunk slots per row starting at the first partial one
-        static_assert(SPR <= 64 && 64 % SPR == 0, "block width must tile a wavefront");
-        constexpr int RPW = 64 / SPR;   // rows per wave pass
+        constexpr int SPR = G::BW / 4;  // chunk slots per row, from the first (maybe partial) one
+        static_assert(NT % SPR == 0, "threads must tile whole block rows");
+        constexpr int RPP = NT / SPR;   // rows per pass of the workgroup
         const int m = off & 3;
-        const int kslot = (off >> 2) + lane % SPR;  // LDS chunk index of this lane
+        const int slot = threadIdx.x % SPR;
+        const int kslot = (off >> 2) + slot;  // LDS chunk index of this thread
         int gc = gxa + 4 * kslot;
         if (gc >= L) gc -= L;
-        const bool partial = (lane % SPR == 0) && m != 0;
-        for (int r = wave * RPW + lane / SPR; r < G::BH; r += NW * RPW) {
+        const bool partial = slot == 0 && m != 0;
+        for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
             int gy = gy0 + G::RING + r;
             if (gy >= L) gy -= L;
             int32_t *row = hout + (size_t)gy * L;
             const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
             const int4 v = Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref);
             if (!partial) {
-                *reinterpret_cast<int4 *>(row + gc) = v;
+                store4_stream(row + gc, v);
             } else {
                 if (m <= 1) row[gc + 1] = v.y;
                 if (m <= 2) row[gc + 2] = v.z;
@@ -389,13 +455,16 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         atomicAdd(a + 1, (unsigned long long)S2inc);
         atomicAdd(a + 2, (unsigned long long)A);
     }
+    __syncthreads();  // LDS is reused by the next queued block
+    }
 }
 
 // Folds each active surface's accumulated increments into its log (the
 // record of t+1 is the record of t plus the increments), clears them and
 // advances t.  One 64-thread workgroup per surface.
-__global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs)
+__global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs, int *__restrict__ queue)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0;
     SurfDev &d = descs[blockIdx.x];
     const long long t = d.t;
     if (t >= d.t_end) return;

@@ -1,0 +1,70 @@
+"""Summaries of rocprofv3 counter runs of the sweep kernel.
+
+`summarize_traffic` reads the CSV output of two `rocprofv3 --pmc` runs of
+`bench.py --copy-probe` (one with FETCH_SIZE, one with WRITE_SIZE), scales
+each counter by what it reads for the probe's plain 1 GiB device copy, and
+returns the HBM bytes per block_sweep launch.  The result is stamped with a
+hash of the kernel source so that a stale measurement is never reported for
+a changed kernel.
+
+    python -m paper_1605_02620_amd.profiling <fetch_dir> <write_dir> <out.json>
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(PKG, "csrc", "rsos_kernels.hpp")
+COPY_BYTES = 1 << 30  # the probe copies one int32[16384^2] buffer
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def _counter(dirname: str, name: str):
+    rows = list(csv.DictReader(open(os.path.join(dirname, "run_counter_collection.csv"))))
+    sweep = [float(r["Counter_Value"]) for r in rows
+             if r["Counter_Name"] == name and "block_sweep" in r["Kernel_Name"]]
+    copies = sorted(float(r["Counter_Value"]) for r in rows
+                    if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"])
+    kernel = next(r["Kernel_Name"] for r in rows if "block_sweep" in r["Kernel_Name"])
+    if not sweep or len(copies) < 5:
+        raise ValueError(f"{dirname}: no block_sweep or probe-copy dispatches for {name}")
+    probe = sum(copies[-5:]) / 5.0  # the five 1 GiB copies are the largest
+    scale = (COPY_BYTES / 1024.0) / probe
+    return kernel, sum(sweep) / len(sweep) * 1024.0 * scale, scale
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str) -> dict:
+    kernel, fetch, sf = _counter(fetch_dir, "FETCH_SIZE")
+    _, write, sw = _counter(write_dir, "WRITE_SIZE")
+    return {"kernel": kernel, "kernel_source_sha256_16": kernel_hash(),
+            "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+            "traffic_bytes_per_launch": round(fetch + write),
+            "fetch_scale": round(sf, 4), "write_scale": round(sw, 4)}
+
+
+def current_traffic(json_path: str):
+    """Bytes per launch from a stored summary, or None if the kernel source
+    changed since the counters were taken."""
+    try:
+        d = json.load(open(json_path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return d
+
+
+if __name__ == "__main__":
+    if len(sys.argv) != 4:
+        print(__doc__)
+        sys.exit(2)
+    out = summarize_traffic(sys.argv[1], sys.argv[2])
+    json.dump(out, open(sys.argv[3], "w"), indent=1)
+    print(json.dumps(out))

@@ -90,6 +90,11 @@ class Surface:
         """The current state as a device tensor (a view of one of the buffers)."""
         return self.bufs[self.time() & 1]
 
+    def kernel_name(self) -> str:
+        buf = ctypes.create_string_buffer(128)
+        check(lib().rsos_kernel_name(self._h, buf, 128))
+        return buf.value.decode()
+
     def timing(self, enable: bool = True):
         """Brackets every tile-block kernel launch with HIP events."""
         check(lib().rsos_timing(self._h, int(bool(enable))))

@@ -81,6 +81,20 @@ def test_surface_matches_oracle(rsos, oracle, L, N, D, seed, sweeps, start):
     s.close()
 
 
+@pytest.mark.parametrize("L,N,height", [(1024, 2, 900), (2048, 1, 700), (512, 4, 2000)])
+def test_mixed_staging_widths(rsos, oracle, L, N, height):
+    """A cone: blocks near the apex exceed the narrow LDS staging and are
+    re-run with wider staging, flat blocks are not; both agree with the
+    oracle bit for bit, over sweeps that move the cone's slopes."""
+    _say(f"cone L={L} N={N} height={height}")
+    h0 = workloads.cone(L, N, height, seed=L + N)
+    s = rsos.Surface(L, N=N, seed=99, D=8, h0=h0)
+    s.sweep(6)
+    r_h, r_log = _oracle_run(oracle, h0, L, N, 8, 99, 0, 6)
+    _compare(s.log(1, 6), r_log, s.heights(), r_h, L)
+    s.close()
+
+
 def test_graph_replay_and_split_calls(rsos, oracle):
     """Sweeps issued as one long call on a side stream (hipGraph replays of
     32 sweeps), as many short calls, and as a mix give the same bits."""

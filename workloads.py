@@ -61,6 +61,19 @@ def rough(L: int, N: int, seed: int, base: int = 0, amp: int | None = None) -> n
     return np.ascontiguousarray(h.reshape(-1).astype(np.int32))
 
 
+def cone(L: int, N: int, height: int, seed: int = 0) -> np.ndarray:
+    """A Manhattan cone h = max(0, height - N |x - cx| - N |y - cy|) around a
+    seeded centre (periodic distance): every bond differs by at most N, steep
+    near the apex and flat far from it."""
+    rng = np.random.default_rng(seed)
+    cx, cy = (int(v) for v in rng.integers(0, L, size=2))
+    x = np.arange(L)
+    dx = np.minimum((x - cx) % L, (cx - x) % L)
+    dy = np.minimum((x - cy) % L, (cy - x) % L)
+    h = np.maximum(0, height - N * (dx[None, :] + dy[:, None]))
+    return np.ascontiguousarray(h.reshape(-1).astype(np.int32))
+
+
 def violating(L: int, N: int, seed: int) -> np.ndarray:
     """A surface with exactly one bond whose height difference exceeds N."""
     rng = np.random.default_rng(seed)
