@@ -15,7 +15,9 @@ Printed JSON line (one): attempts per ns over the timed region, plus
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
                 (a few sweeps of the same surface), all host cores;
   batched       the ensemble of 256 surfaces (L in {256..2048}) in one launch
-                per sweep versus the same surfaces one surface per launch.
+                per sweep versus the same surfaces one surface per launch;
+  served        a Poisson stream of jobs through the continuous-batching
+                engine: p50/p99 latency from arrival and aggregate rate.
 """
 from __future__ import annotations
 
@@ -103,6 +105,34 @@ def bench_batched(n_steps_batch=200):
             "batched_over_plain": round(rate_b / rate_p, 3)}
 
 
+def bench_served(n_jobs=200, load=0.9, capacity_attempts_per_ns=None, pool_gib=8):
+    """The served workload's job mix (L a power of two in [128, 8192], N in
+    {1, 2, 4}, t_max log-uniform) as a Poisson stream at `load` times the
+    plain path's capacity, through the continuous-batching engine.
+    t_max is drawn from [100, 2000] (the full workload's [100, 20000] with
+    2000 jobs runs for minutes) so the default run stays short."""
+    import numpy as np
+    import torch
+    from paper_1605_02620_amd import serve
+    import workloads
+    probe = workloads.job_stream(n_jobs=n_jobs, rate_per_s=1.0, seed=5, t_range=(100, 2000))
+    mean_attempts = float(np.mean([j.L * j.L * j.t_max for j in probe]))
+    cap = capacity_attempts_per_ns or 400.0
+    rate = load * cap * 1e9 / mean_attempts  # jobs per second
+    jobs = workloads.job_stream(n_jobs=n_jobs, rate_per_s=rate, seed=5, t_range=(100, 2000))
+    eng = serve.Engine(pool_bytes=pool_gib << 30, max_running=256, D=8)
+    res, summ = serve.serve(eng, jobs, grid=lambda tm: workloads.pow2_grid(tm))
+    eng.close()
+    torch.cuda.synchronize()
+    return {"workload": f"{n_jobs} jobs, Poisson arrivals at {rate:.2f}/s ({load} x the plain "
+                        f"capacity {cap:.0f} attempts/ns), L = 2^7..2^13, N in {{1,2,4}}, "
+                        f"t_max log-uniform in [100, 2000], {pool_gib} GiB pool",
+            "jobs_done": summ["jobs_done"], "wall_s": round(summ["wall_s"], 3),
+            "attempts_per_ns": round(summ["attempts_per_ns"], 2),
+            "latency_p50_s": round(summ["latency_p50_s"], 4),
+            "latency_p99_s": round(summ["latency_p99_s"], 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +140,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -190,6 +221,11 @@ def main():
         del src, dst
     if not args.no_batch:
         out["batched"] = bench_batched()
+    if not args.no_serve:
+        # capacity of the plain path: one surface per launch at the rate the
+        # single large surface reaches (the job mix's attempts are dominated
+        # by its largest lattices)
+        out["served"] = bench_served(capacity_attempts_per_ns=value)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, N, D, seed)
     print(json.dumps(out), flush=True)

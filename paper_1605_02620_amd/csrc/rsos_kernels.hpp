@@ -75,6 +75,31 @@ __host__ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1
 // ---------------------------------------------------------------------------
 constexpr int kAccSlots = 64;  // per-surface spread of the (S1, S2, A) atomics
 
+// Lattice pointers reach the kernels through descriptors in memory, so the
+// compiler sees generic pointers and would emit flat memory instructions
+// (which also count against the LDS wait counter).  They always point to
+// device global memory: accesses go through these global-address-space
+// views.
+typedef __attribute__((address_space(1))) int32_t gint32;
+typedef __attribute__((address_space(1))) unsigned long long gu64;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4i gv4i;
+
+__device__ __forceinline__ const gint32 *as_global(const int32_t *p) { return (const gint32 *)p; }
+__device__ __forceinline__ gint32 *as_global(int32_t *p) { return (gint32 *)p; }
+
+__device__ __forceinline__ int4 load4(const gint32 *p)
+{
+    const v4i x = *reinterpret_cast<const gv4i *>(p);
+    return make_int4(x.x, x.y, x.z, x.w);
+}
+
+__device__ __forceinline__ void store4(gint32 *p, const int4 v)
+{
+    const v4i x = {v.x, v.y, v.z, v.w};
+    *reinterpret_cast<gv4i *>(p) = x;
+}
+
 struct SurfDev {
     int32_t *buf[2];      // state after t sweeps is in buf[t & 1]
     long long *log;       // 3 * log_cap int64: (S1, S2, A) of time tau at slot tau % log_cap
@@ -241,11 +266,10 @@ template <> struct Lds4<int32_t> {
 
 // The next sweep reads the output from HBM long after this one wrote it:
 // stream the full 16-byte chunks past the caches.
-__device__ __forceinline__ void store4_stream(int32_t *dst, const int4 v)
+__device__ __forceinline__ void store4_stream(gint32 *dst, const int4 v)
 {
-    typedef int v4i __attribute__((ext_vector_type(4)));
     const v4i x = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(dst));
+    __builtin_nontemporal_store(x, reinterpret_cast<gv4i *>(dst));
 }
 
 // ---------------------------------------------------------------------------
@@ -300,8 +324,8 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     const int L = d.L, N = d.N, T = d.T;
     const uint32_t s = (uint32_t)t;
     const uint32_t k0 = d.key0, k1 = d.key1;
-    const int32_t *__restrict__ hin = d.buf[t & 1];
-    int32_t *__restrict__ hout = d.buf[(t + 1) & 1];
+    const gint32 *__restrict__ hin = as_global(d.buf[t & 1]);
+    gint32 *__restrict__ hout = as_global(d.buf[(t + 1) & 1]);
 
     const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
     const int ox = (int)(org.v[0] % (2u * D));
@@ -332,7 +356,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
                     const int r = i / G::CH, cc = i - r * G::CH;
                     int gy = gy0 + r; if (gy >= L) gy -= L;
                     int gx = gxa + 4 * cc; if (gx >= L) gx -= L;
-                    v[u] = *reinterpret_cast<const int4 *>(hin + (size_t)gy * L + gx);
+                    v[u] = load4(hin + (size_t)gy * L + gx);
                 }
             }
 #pragma unroll
@@ -415,14 +439,25 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         int gc = gxa + 4 * kslot;
         if (gc >= L) gc -= L;
         const bool partial = slot == 0 && m != 0;
+        // chunks whose 128-byte line lies wholly inside the block row are
+        // streamed past the caches; lines shared with the neighbouring block
+        // go through L2, where the two halves merge (row bases are
+        // line-aligned when L % 32 == 0)
+        const int row_lo = 4 * (gxa + off), row_hi = row_lo + 4 * G::BW;
+        const int line = (4 * (gxa + 4 * kslot)) & ~127;
+        const bool whole_line = (L % 32 == 0) && line >= row_lo && line + 128 <= row_hi &&
+                                gxa + off + G::BW <= L;
         for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
             int gy = gy0 + G::RING + r;
             if (gy >= L) gy -= L;
-            int32_t *row = hout + (size_t)gy * L;
+            gint32 *row = hout + (size_t)gy * L;
             const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
             const int4 v = Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref);
             if (!partial) {
-                store4_stream(row + gc, v);
+                if (whole_line)
+                    store4_stream(row + gc, v);
+                else
+                    store4(row + gc, v);
             } else {
                 if (m <= 1) row[gc + 1] = v.y;
                 if (m <= 2) row[gc + 2] = v.z;
@@ -437,7 +472,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
             for (int r = threadIdx.x; r < G::BH; r += NT) {
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
-                int32_t *row = hout + (size_t)gy * L;
+                gint32 *row = hout + (size_t)gy * L;
                 const E *src = lds + (G::RING + r) * G::RWL + 4 * kt;
                 row[gct] = ref + (int)src[0];
                 if (m >= 2) row[gct + 1] = ref + (int)src[1];
@@ -450,10 +485,10 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     block_reduce3<NT>(A, S2inc, unused);
     if (threadIdx.x == 0) {
         S2inc += 2ll * ref * A;
-        unsigned long long *a = reinterpret_cast<unsigned long long *>(d.acc + 3 * (b & (kAccSlots - 1)));
-        atomicAdd(a + 0, (unsigned long long)A);
-        atomicAdd(a + 1, (unsigned long long)S2inc);
-        atomicAdd(a + 2, (unsigned long long)A);
+        gu64 *a = (gu64 *)(d.acc + 3 * (b & (kAccSlots - 1)));
+        __hip_atomic_fetch_add(a + 0, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a + 1, (unsigned long long)S2inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a + 2, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();  // LDS is reused by the next queued block
     }
