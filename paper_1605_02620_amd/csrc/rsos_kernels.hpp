@@ -343,34 +343,46 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
 
     int vmin = 0x7FFFFFFF, vmax = -0x7FFFFFFF;  // range of the staged heights (int8 staging)
     // ---- load the region in aligned 16-byte chunks, consecutive threads on
-    // consecutive chunks (rows run on into the next), U chunks in flight
+    // consecutive chunks (rows run on into the next), U chunks in flight per
+    // thread; chunk i sits at region row i / CH, chunk column i % CH
     {
         constexpr int NCH = G::CH * G::RH;
         constexpr int U = 8;
-        for (int i0 = threadIdx.x; i0 < NCH; i0 += NT * U) {
+        constexpr int FULL = NCH / (NT * U);  // groups in which every thread has U chunks
+        auto fetch = [&](int i) {
+            const int r = i / G::CH, cc = i - r * G::CH;
+            int gy = gy0 + r;
+            if (gy >= L) gy -= L;
+            int gx = gxa + 4 * cc;
+            if (gx >= L) gx -= L;
+            return load4(hin + (size_t)gy * L + gx);
+        };
+        auto stage = [&](int i, const int4 &v) {
+            const int r = i / G::CH, cc = i - r * G::CH;
+            lds_put4<E>(lds + r * G::RWL + 4 * cc, v, ref);
+            if (StageLimits<E>::checked) {
+                vmin = min(vmin, min(min(v.x, v.y), min(v.z, v.w)));
+                vmax = max(vmax, max(max(v.x, v.y), max(v.z, v.w)));
+            }
+        };
+#pragma unroll 1
+        for (int g = 0; g < FULL; ++g) {
+            const int i0 = g * NT * U + threadIdx.x;
             int4 v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * NT;
-                if (i < NCH) {
-                    const int r = i / G::CH, cc = i - r * G::CH;
-                    int gy = gy0 + r; if (gy >= L) gy -= L;
-                    int gx = gxa + 4 * cc; if (gx >= L) gx -= L;
-                    v[u] = load4(hin + (size_t)gy * L + gx);
-                }
-            }
+            for (int u = 0; u < U; ++u) v[u] = fetch(i0 + u * NT);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * NT;
-                if (i < NCH) {
-                    const int r = i / G::CH, cc = i - r * G::CH;
-                    lds_put4<E>(lds + r * G::RWL + 4 * cc, v[u], ref);
-                    if (StageLimits<E>::checked) {
-                        vmin = min(vmin, min(min(v[u].x, v[u].y), min(v[u].z, v[u].w)));
-                        vmax = max(vmax, max(max(v[u].x, v[u].y), max(v[u].z, v[u].w)));
-                    }
-                }
-            }
+            for (int u = 0; u < U; ++u) stage(i0 + u * NT, v[u]);
+        }
+        {
+            const int i0 = FULL * NT * U + threadIdx.x;
+            int4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u * NT < NCH) v[u] = fetch(i0 + u * NT);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u * NT < NCH) stage(i0 + u * NT, v[u]);
         }
     }
     if (StageLimits<E>::checked) {
