@@ -17,7 +17,12 @@ Printed JSON line (one): attempts per ns over the timed region, plus
   batched       the ensemble of 256 surfaces (L in {256..2048}) in one launch
                 per sweep versus the same surfaces one surface per launch;
   served        a Poisson stream of jobs through the continuous-batching
-                engine: p50/p99 latency from arrival and aggregate rate.
+                engine: p50/p99 latency from arrival and aggregate rate;
+  packed16      the same surface and sweeps with heights kept on the device
+                as 16-bit residues (identical results, 4 B per attempt), with
+                its own roofline.
+--storage packed16 makes the 16-bit surface the headline (for profiling it
+alone).
 """
 from __future__ import annotations
 
@@ -64,6 +69,57 @@ def cpu_baseline(L, N, D, seed, budget_s=12.0):
             "cores": threads, "kind": "oracle",
             "sample": f"first {sweeps} sweeps of the L={L} N={N} D={D} surface from flat, "
                       f"{dt:.1f} s, OpenMP over the tiles of a phase"}
+
+
+def _traffic(kname, packed):
+    """Measured HBM bytes per launch from the committed counter summary, only
+    while it describes this kernel source and instance."""
+    from paper_1605_02620_amd import profiling
+    name = "block_sweep16_traffic.json" if packed else "block_sweep_traffic.json"
+    tr = profiling.current_traffic(os.path.join(ROOT, "profiles", name))
+    rk = (tr or {}).get("kernel", "").replace(" ", "")
+    for a, b in ((",unsignedchar,", ",uint8,"), (",signedchar,", ",int8,"), (",short,", ",int16,"),
+                 (",int,", ",int32,")):
+        rk = rk.replace(a, b)
+    if tr is not None and rk.startswith("voidrsosk::" + kname[:-1] + ","):
+        return tr["traffic_bytes_per_launch"]
+    return None
+
+
+def bench_single(L, N, D, seed, steps, warmup, packed=False):
+    """K sweeps of one surface in one rsos_sweep call (hipGraph replays of
+    the two kernels per sweep), then the same again with every tile-block
+    kernel bracketed by HIP events on the surface's stream (graph replay
+    off) for the dominant kernel's mean duration."""
+    import torch
+    import paper_1605_02620_amd as rsos
+    stream = torch.cuda.Stream()
+    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=max(4096, steps + warmup + 1), stream=stream,
+                     packed=packed)
+    s.sweep(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(steps)
+    s.width()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = L * L * steps / (dt * 1e9)
+    s.timing(True)
+    torch.cuda.synchronize()
+    s.sweep(min(steps, 400))
+    launches, mean_ms, _ = s.timing_read()
+    s.timing(False)
+    w = s.width()
+    kname = s.kernel_name()
+    s.close()
+    bpa = BYTES_PER_ATTEMPT // 2 if packed else BYTES_PER_ATTEMPT
+    achieved = L * L * bpa / (mean_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _traffic(kname, packed), "traffic_unit": "bytes per launch",
+                "kernel": kname, "launches_timed": launches, "kernel_mean_ms": round(mean_ms, 4),
+                "algorithmic_bytes_per_launch": L * L * bpa}
+    return {"value": value, "dt": dt, "w": w, "roofline": roofline}
 
 
 def bench_batched(n_steps_batch=200):
@@ -141,6 +197,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--no-packed", action="store_true", help="skip the 16-bit storage leg")
+    ap.add_argument("--storage", choices=("int32", "packed16"), default="int32",
+                    help="height storage of the headline surface")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -150,54 +209,12 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_1605_02620_amd as rsos
     import workloads
 
     cfg = workloads.cfg_single()
     L, N, D, seed = cfg.L, cfg.N, cfg.D, cfg.seed
-    stream = torch.cuda.Stream()
-    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=max(4096, args.steps + args.warmup + 1),
-                     stream=stream)
-    s.sweep(args.warmup)
-    torch.cuda.synchronize()
-
-    # timed region: K sweeps, hipGraph replays of the two kernels per sweep
-    t0 = time.perf_counter()
-    s.sweep(args.steps)
-    s.width()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    attempts = L * L * args.steps
-    value = attempts / (dt * 1e9)
-
-    # same region again with every tile-block kernel bracketed by HIP events
-    # on the surface's stream (graph replay off): the dominant kernel's
-    # mean duration
-    s.timing(True)
-    torch.cuda.synchronize()
-    k_steps = min(args.steps, 400)
-    s.sweep(k_steps)
-    launches, mean_ms, _ = s.timing_read()
-    s.timing(False)
-    w = s.width()
-    kname = s.kernel_name()
-    s.close()
-    achieved = L * L * BYTES_PER_ATTEMPT / (mean_ms * 1e-3) / 1e9
-    # measured HBM bytes per launch from the committed counter summary, only
-    # while it describes this kernel source and instance
-    from paper_1605_02620_amd import profiling
-    tr = profiling.current_traffic(os.path.join(ROOT, "profiles", "block_sweep_traffic.json"))
-    traffic = None
-    rk = (tr or {}).get("kernel", "").replace(" ", "")
-    rk = rk.replace(",signedchar,", ",int8,").replace(",short,", ",int16,").replace(",int,", ",int32,")
-    if tr is not None and rk.startswith("voidrsosk::" + kname[:-1] + ","):
-        traffic = tr["traffic_bytes_per_launch"]
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch", "kernel": kname, "launches_timed": launches,
-                "kernel_mean_ms": round(mean_ms, 4),
-                "algorithmic_bytes_per_launch": L * L * BYTES_PER_ATTEMPT}
-
+    head = bench_single(L, N, D, seed, args.steps, args.warmup, packed=args.storage == "packed16")
+    value, dt, w, roofline = head["value"], head["dt"], head["w"], head["roofline"]
     out = {"metric": "attempted site updates/ns", "value": round(value, 3),
            "unit": "attempts/ns", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
@@ -206,8 +223,18 @@ def main():
                                   f"start, seed {seed}, {args.steps} sweeps timed after "
                                   f"{args.warmup} warm-up sweeps",
                       "L": L, "N": N, "D": D, "seed": seed, "sweeps": args.steps,
+                      "storage": args.storage,
                       "final_t": int(w["t"]), "final_w2": float(w["w2"])},
            "roofline": roofline}
+    if args.storage == "int32" and not args.no_packed:
+        # the same surface and sweeps with heights kept as 16-bit residues
+        # (identical results; 4 B per attempt)
+        pk = bench_single(L, N, D, seed, args.steps, args.warmup, packed=True)
+        out["packed16"] = {"value": round(pk["value"], 3), "unit": "attempts/ns",
+                           "ms_per_step": round(pk["dt"] * 1e3 / args.steps, 4),
+                           "final_t": int(pk["w"]["t"]), "final_w2": float(pk["w"]["w2"]),
+                           "same_result": bool(pk["w"]["s1"] == w["s1"] and pk["w"]["s2"] == w["s2"]),
+                           "roofline": pk["roofline"]}
     if args.copy_probe:
         src = torch.ones(L * L, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

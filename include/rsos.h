@@ -61,19 +61,33 @@ typedef enum {
 } rsos_status;
 
 /* Parameters of one surface.
- *   L    lattice side, a multiple of 2*D, 2*D <= L <= 65536;
- *   N    step restriction of Sec. I, N >= 1 (INT32_MAX: no restriction);
- *   D    tile side of the domain decomposition, one of 2, 4, 8, 16
- *        (the paper uses 8 x 8 domains, Sec. II, and tests 16 x 16,
- *        Sec. III.C); part of the result;
- *   seed 64-bit Philox key. */
+ *   L     lattice side, a multiple of 2*D, 2*D <= L <= 65536;
+ *   N     step restriction of Sec. I, N >= 1 (INT32_MAX: no restriction);
+ *   D     tile side of the domain decomposition, one of 2, 4, 8, 16
+ *         (the paper uses 8 x 8 domains, Sec. II, and tests 16 x 16,
+ *         Sec. III.C); part of the result;
+ *   flags 0 or RSOS_FLAG_PACKED16 (storage only: results are identical);
+ *   seed  64-bit Philox key. */
 typedef struct {
     int32_t L;
     int32_t N;
     int32_t D;
-    int32_t reserved; /* must be 0 */
+    int32_t flags;
     uint64_t seed;
 } rsos_params;
+
+/* Heights kept in device memory as 16-bit residues mod 2^16 (half the HBM
+ * bytes of a sweep).  Exact: on the torus the restriction keeps every height
+ * within N*L of every other, and the mean moves by at most one per sweep, so
+ * the residue and floor(S1 / L^2) determine each height.  Requires
+ * N*L <= 32766, N*D <= 96, L^2 * 4 > 64 KiB (the tile-block path) and a
+ * tile-block shape for L (RSOS_E_INVAL otherwise).  Single surfaces and
+ * batches; the serving engine keeps int32.  Buffer roles change: d_h (or a
+ * batch surface's slice of d_pool) holds both residue buffers, and d_work
+ * (or d_work_pool) is the int32 scratch that rsos_heights converts into
+ * before a host copy (and that receives h0_host at init).  rsos_time's
+ * d_current is NULL in this mode. */
+#define RSOS_FLAG_PACKED16 1
 
 /* One record of the per-sweep log: the state after t sweeps.
  *   s1 = sum h, s2 = sum h^2 (exact), accepted = accepted attempts of sweep
@@ -128,7 +142,8 @@ rsos_status rsos_log(rsos_surface *s, int64_t t_from, int64_t n, rsos_width_t *o
  * device memory as dst_is_device says. */
 rsos_status rsos_heights(rsos_surface *s, int32_t *dst, int dst_is_device);
 
-/* Current time t and the device buffer that holds the current state. */
+/* Current time t and the device buffer that holds the current int32 state
+ * (NULL with RSOS_FLAG_PACKED16). */
 rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current);
 
 /* Kernel timing.  While enabled, every tile-block sweep kernel launch of
@@ -154,7 +169,7 @@ rsos_status rsos_free(rsos_surface *s);
 /* one launch per sweep.  Independent realization sets, Sec. II.          */
 /* --------------------------------------------------------------------- */
 
-/* n surfaces; p[i] their parameters (all with the same D);
+/* n surfaces; p[i] their parameters (all with the same D and flags);
  * d_pool / d_work_pool caller-owned device int32 pools, surface i at
  * element offsets[i] of each (L_i^2 elements, offsets[] host array);
  * d_work_pool NULL makes the library allocate the second pool.  Flat start,

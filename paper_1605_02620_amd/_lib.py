@@ -23,10 +23,11 @@ P = ctypes.POINTER
 
 OK, E_INVAL, E_RSOS, E_OVERFLOW, E_DEVICE, E_NOMEM, E_STATE, E_BUSY = 0, -1, -2, -3, -4, -5, -6, -7
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
+FLAG_PACKED16 = 1
 
 
 class Params(ctypes.Structure):
-    _fields_ = [("L", c_i32), ("N", c_i32), ("D", c_i32), ("reserved", c_i32), ("seed", c_u64)]
+    _fields_ = [("L", c_i32), ("N", c_i32), ("D", c_i32), ("flags", c_i32), ("seed", c_u64)]
 
 
 class Width(ctypes.Structure):

@@ -59,45 +59,63 @@ void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue
     hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, queue);
 }
 
+template <int D, int TX, int TY, int NT, typename E, bool FB>
+void launch_block16(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue)
+{
+    hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, queue);
+}
+
 struct Variant {
     int D, TX, TY, NT, elem;  // elem: LDS bytes per site (1 and 2: offsets from a block reference)
     BlockLaunch launch;
     BlockLaunch fallback;     // for elem == 1: the same blocks with wider staging
     int fb_elem;
+    // 16-bit storage: uint8 staging with an int16 fallback (nullptr: the
+    // shape is not offered for 16-bit storage)
+    BlockLaunch launch16;
+    BlockLaunch fallback16;
 };
 
 // int8 staging checks every block's range and queues the few that do not
 // fit for a second launch of the same block shape with int16 (or int32)
 // staging.
+#define P16(D, TX, TY, NT) \
+    launch_block16<D, TX, TY, NT, uint8_t, false>, launch_block16<D, TX, TY, NT, int16_t, true>
 #define V8(D, TX, TY, NT)                                                                     \
     {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
-     launch_block<D, TX, TY, NT, int16_t, true>, 2}
+     launch_block<D, TX, TY, NT, int16_t, true>, 2, P16(D, TX, TY, NT)}
 #define V8W(D, TX, TY, NT)                                                                    \
     {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
-     launch_block<D, TX, TY, NT, int32_t, true>, 4}
-#define V16(D, TX, TY, NT) {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0}
-#define V32(D, TX, TY, NT) {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, false>, nullptr, 0}
+     launch_block<D, TX, TY, NT, int32_t, true>, 4, nullptr, nullptr}
+#define V16(D, TX, TY, NT) {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, nullptr, nullptr}
+#define V16P(D, TX, TY, NT) \
+    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, P16(D, TX, TY, NT)}
+#define V32(D, TX, TY, NT) {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, false>, nullptr, 0, nullptr, nullptr}
 // In order of preference; the first one that fits every surface is used.
 const Variant kVariants[] = {
-    V16(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
-    V16(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64),
-    V8(8, 32, 8, 192), V8W(8, 32, 8, 192), V16(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
+    V16P(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
+    V16P(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64),
+    V8(8, 32, 8, 192), V8W(8, 32, 8, 192), V16P(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
     V32(8, 8, 8, 64), V32(8, 2, 2, 64),
-    V16(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
+    V16P(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
 };
+#undef P16
 #undef V8
 #undef V8W
 #undef V16
+#undef V16P
 #undef V32
 
-bool variant_fits(const Variant &v, int L, int N)
+bool variant_fits(const Variant &v, int L, int N, bool packed)
 {
     const int T = L / v.D;
     const int rw = v.TX * v.D + 2 * (v.D + 1), rh = v.TY * v.D + 2 * (v.D + 1);
-    const int rwl = (rw + 6) & ~3;
+    const int rwl = packed ? (rw + 14) & ~7 : (rw + 6) & ~3;
     if (T % v.TX != 0 || T % v.TY != 0 || rwl > L || rh > L) return false;
     // int16 staging: every staged value within 32767 of the block reference
     const bool i16_ok = (long long)N * (rw + rh + 4) + v.D * v.D <= 32767;
+    // 16-bit storage: uint8 staging (N D <= 96) and the int16 fallback
+    if (packed) return v.launch16 && L % 8 == 0 && (long long)N * v.D <= 96 && i16_ok;
     if (v.elem == 2 && !i16_ok) return false;
     // int8 staging: the sweep's growth N D must leave room in the byte; the
     // fallback's wider type must hold the blocks that still do not fit
@@ -106,22 +124,39 @@ bool variant_fits(const Variant &v, int L, int N)
 }
 
 // First fitting variant for D that fits every (L, N) (optionally forced by
-// the RSOS_VARIANT environment variable "TXxTYxNTxELEM", e.g. "16x8x128x2").
-const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN)
+// the RSOS_VARIANT environment variable "TXxTYxNTxELEM", e.g. "16x8x128x2";
+// ELEM is 16 for the 16-bit storage kernels).
+const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN, bool packed = false)
 {
     const char *force = getenv("RSOS_VARIANT");
     for (const Variant &v : kVariants) {
         if (v.D != D) continue;
         if (force) {
             char want[48];
-            snprintf(want, sizeof want, "%dx%dx%dx%d", v.TX, v.TY, v.NT, v.elem);  // e.g. 32x8x192x1
+            snprintf(want, sizeof want, "%dx%dx%dx%d", v.TX, v.TY, v.NT, packed ? 16 : v.elem);
             if (strcmp(force, want) != 0) continue;
         }
         bool ok = true;
-        for (auto &ln : LN) ok = ok && variant_fits(v, ln.first, ln.second);
+        for (auto &ln : LN) ok = ok && variant_fits(v, ln.first, ln.second, packed);
         if (ok) return &v;
     }
     return nullptr;
+}
+
+bool uses_lds(int L);
+
+// 16-bit storage is exact while every height of a sweep stays within 2^15
+// of floor(mean): N L <= 32766 (the torus spread is at most N L, the mean
+// moves by at most one per sweep).
+rsos_status check_packed(const rsos_params *p)
+{
+    if (uses_lds(p->L))
+        return fail(RSOS_E_INVAL, "16-bit storage: L=%d is small enough for the LDS path, which keeps int32", p->L);
+    if ((long long)p->N * p->L > 32766)
+        return fail(RSOS_E_INVAL, "16-bit storage needs N*L <= 32766 (N=%d, L=%d)", p->N, p->L);
+    if (!pick_variant(p->D, {{p->L, p->N}}, true))
+        return fail(RSOS_E_INVAL, "16-bit storage: no tile-block shape fits L=%d, N=%d, D=%d", p->L, p->N, p->D);
+    return RSOS_OK;
 }
 
 typedef void (*LdsLaunch)(dim3, size_t, hipStream_t, SurfDev *, const int *);
@@ -150,7 +185,8 @@ rsos_status check_params(const rsos_params *p)
     if (p->L < 2 * p->D || p->L > 65536 || p->L % (2 * p->D) != 0)
         return fail(RSOS_E_INVAL, "L=%d: must be a multiple of 2D=%d in [2D, 65536]", p->L, 2 * p->D);
     if (p->N < 1) return fail(RSOS_E_INVAL, "N=%d: must be >= 1", p->N);
-    if (p->reserved != 0) return fail(RSOS_E_INVAL, "reserved field must be 0");
+    if (p->flags & ~RSOS_FLAG_PACKED16) return fail(RSOS_E_INVAL, "unknown flags 0x%x", (unsigned)p->flags);
+    if (p->flags & RSOS_FLAG_PACKED16) return check_packed(p);
     return RSOS_OK;
 }
 
@@ -246,12 +282,14 @@ struct Staging {
 // ---------------------------------------------------------------------------
 struct SurfaceGroup {
     int D = 8;
+    bool packed = false;               // heights kept as 16-bit residues
     hipStream_t stream = nullptr;
     bool failed = false;
     std::vector<SurfDev> host;         // host mirror (t, t_end kept current)
     std::vector<long long> max_h0, t0; // per surface
     SurfDev *d_desc = nullptr;
-    long long *d_acc = nullptr;        // kAccSlots x 3 accumulators per block-path surface
+    long long *d_acc = nullptr;        // kAccWords per block-path surface
+    std::vector<int32_t *> readout;    // 16-bit storage: int32[L^2] device scratch per surface
     int *d_queue = nullptr;            // blocks handed to the wider fallback launch
     std::vector<int> lds_idx, blk_idx; // surfaces on each path
     int *d_lds_idx = nullptr;
@@ -287,9 +325,10 @@ struct SurfaceGroup {
                     return fail(RSOS_E_INVAL, "height buffers must be 16-byte aligned");
         }
         if (!blk_idx.empty()) {
-            variant = pick_variant(D, LN);
+            variant = pick_variant(D, LN, packed);
             if (!variant) return fail(RSOS_E_INVAL, "no tile-block shape fits these lattice sizes");
         }
+        if (packed && !lds_idx.empty()) return fail(RSOS_E_INVAL, "16-bit storage needs the tile-block path");
         // block path surfaces first in the table, sorted by block_start
         long long blocks = 0;
         for (int i : blk_idx) {
@@ -310,11 +349,11 @@ struct SurfaceGroup {
         rsos_status st;
         if ((st = dev_alloc((void **)&d_desc, sizeof(SurfDev) * n)) != RSOS_OK) return st;
         if (!blk_idx.empty()) {
-            const size_t bytes = sizeof(long long) * 3 * rsosk::kAccSlots * blk_idx.size();
+            const size_t bytes = sizeof(long long) * rsosk::kAccWords * blk_idx.size();
             if ((st = dev_alloc((void **)&d_acc, bytes)) != RSOS_OK) return st;
             HIP_TRY(hipMemset(d_acc, 0, bytes));
             for (size_t k = 0; k < blk_idx.size(); ++k)
-                host[blk_idx[k]].acc = d_acc + 3 * rsosk::kAccSlots * k;
+                host[blk_idx[k]].acc = d_acc + rsosk::kAccWords * k;
             if ((st = dev_alloc((void **)&d_queue, sizeof(int) * (1 + (size_t)total_blocks))) != RSOS_OK)
                 return st;
             HIP_TRY(hipMemset(d_queue, 0, sizeof(int)));
@@ -393,10 +432,10 @@ struct SurfaceGroup {
     void launch_block_sweep()
     {
         const int n = (int)blk_idx.size();
-        variant->launch(dim3(total_blocks), stream, d_desc, n, d_queue);
-        if (variant->fallback)
-            variant->fallback(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n,
-                              d_queue);
+        BlockLaunch main = packed ? variant->launch16 : variant->launch;
+        BlockLaunch fb = packed ? variant->fallback16 : variant->fallback;
+        main(dim3(total_blocks), stream, d_desc, n, d_queue);
+        if (fb) fb(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n, d_queue);
     }
 
     rsos_status enqueue_one()
@@ -464,12 +503,52 @@ struct SurfaceGroup {
     rsos_status copy_heights(int i, int32_t *dst, int dst_is_device)
     {
         const SurfDev &s = host[i];
+        const size_t n = (size_t)s.L * s.L;
+        if (packed) {
+            // residues -> int32 on the device (needs floor(S1 / L^2) of time t)
+            int32_t *out = dst_is_device ? dst : readout[i];
+            hipLaunchKernelGGL(rsosk::unpack16, dim3(grid_for(n)), dim3(256), 0, stream,
+                               (const uint16_t *)s.buf[s.t & 1], out, (long long)n,
+                               (const long long *)(s.acc + rsosk::kMeanWord));
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (!dst_is_device) HIP_TRY(hipMemcpy(dst, out, n * 4, hipMemcpyDeviceToHost));
+            return RSOS_OK;
+        }
         HIP_TRY(hipStreamSynchronize(stream));
-        const size_t bytes = (size_t)s.L * s.L * 4;
-        HIP_TRY(hipMemcpy(dst, s.buf[s.t & 1], bytes,
+        HIP_TRY(hipMemcpy(dst, s.buf[s.t & 1], n * 4,
                           dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
         return RSOS_OK;
     }
+
+    // Initial state of surface i into its buffer of parity t: int32 heights
+    // from host memory (nullptr: flat), as residues in 16-bit storage, and
+    // floor(S1 / L^2) into the accumulator area.
+    rsos_status load_initial(int i, const int32_t *h0_host, long long s1)
+    {
+        const SurfDev &s = host[i];
+        const size_t n = (size_t)s.L * s.L;
+        int32_t *cur = s.buf[s.t & 1];
+        if (!packed) {
+            HIP_TRY(h0_host ? hipMemcpyAsync(cur, h0_host, n * 4, hipMemcpyHostToDevice, stream)
+                            : hipMemsetAsync(cur, 0, n * 4, stream));
+        } else if (h0_host) {
+            HIP_TRY(hipMemcpyAsync(readout[i], h0_host, n * 4, hipMemcpyHostToDevice, stream));
+            hipLaunchKernelGGL(rsosk::pack16, dim3(grid_for(n)), dim3(256), 0, stream,
+                               (const int32_t *)readout[i], (uint16_t *)cur, (long long)n);
+            HIP_TRY(hipGetLastError());
+        } else {
+            HIP_TRY(hipMemsetAsync(cur, 0, n * 2, stream));
+        }
+        if (s.acc) {
+            const long long m0 = s1 / ((long long)s.L * s.L);
+            HIP_TRY(hipMemcpyAsync(s.acc + rsosk::kMeanWord, &m0, sizeof m0, hipMemcpyHostToDevice, stream));
+        }
+        HIP_TRY(hipStreamSynchronize(stream));
+        return RSOS_OK;
+    }
+
+    static unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 8192); }
 
     // Writes the initial log record (time t0) of surface i.
     rsos_status init_record(int i, long long s1, long long s2)
@@ -588,12 +667,21 @@ rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, in
     s->p = *p;
     SurfaceGroup &g = s->g;
     g.D = p->D;
+    g.packed = (p->flags & RSOS_FLAG_PACKED16) != 0;
     g.stream = (hipStream_t)stream;
     const size_t n = (size_t)p->L * p->L;
     SurfDev d = {};
-    d.buf[0] = d_h;
-    d.buf[1] = d_work;
-    if (!d_work && (st = g.dev_alloc((void **)&d.buf[1], n * 4)) != RSOS_OK) { g.destroy(); delete s; return st; }
+    int32_t *work = d_work;
+    if (!work && (st = g.dev_alloc((void **)&work, n * 4)) != RSOS_OK) { g.destroy(); delete s; return st; }
+    if (g.packed) {
+        // both residue buffers in d_h; d_work receives int32 heights on readout
+        d.buf[0] = d_h;
+        d.buf[1] = (int32_t *)((uint16_t *)d_h + n);
+        g.readout.push_back(work);
+    } else {
+        d.buf[0] = d_h;
+        d.buf[1] = work;
+    }
     if ((st = g.dev_alloc((void **)&d.log, sizeof(long long) * 3 * log_cap)) != RSOS_OK) { g.destroy(); delete s; return st; }
     d.log_cap = log_cap;
     d.t = t0;
@@ -608,15 +696,7 @@ rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, in
     g.t0.push_back(t0);
     if ((st = mark(g, g.setup())) != RSOS_OK) { g.destroy(); delete s; return st; }
     // initial state into the buffer of parity t0
-    int32_t *cur = d.buf[t0 & 1];
-    hipError_t e = h0_host ? hipMemcpyAsync(cur, h0_host, n * 4, hipMemcpyHostToDevice, g.stream)
-                           : hipMemsetAsync(cur, 0, n * 4, g.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
-    if (e != hipSuccess) {
-        g.destroy();
-        delete s;
-        return fail(RSOS_E_DEVICE, "initial copy: %s", hipGetErrorString(e));
-    }
+    if ((st = g.load_initial(0, h0_host, s1)) != RSOS_OK) { g.destroy(); delete s; return st; }
     if ((st = g.init_record(0, s1, s2)) != RSOS_OK) { g.destroy(); delete s; return st; }
     *out = s;
     return RSOS_OK;
@@ -664,7 +744,7 @@ rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current)
     CHECK_HANDLE(s, s->g);
     const SurfDev &d = s->g.host[0];
     if (t) *t = d.t;
-    if (d_current) *d_current = d.buf[d.t & 1];
+    if (d_current) *d_current = s->g.packed ? nullptr : d.buf[d.t & 1];
     return RSOS_OK;
 }
 
@@ -686,7 +766,10 @@ rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len)
     CHECK_HANDLE(s, s->g);
     if (!buf || len < 1) return fail(RSOS_E_INVAL, "bad buffer");
     const SurfaceGroup &g = s->g;
-    if (g.variant)
+    if (g.variant && g.packed)
+        snprintf(buf, (size_t)len, "block_sweep16<%d,%d,%d,%d,uint8>", g.variant->D, g.variant->TX,
+                 g.variant->TY, g.variant->NT);
+    else if (g.variant)
         snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s>", g.variant->D, g.variant->TX,
                  g.variant->TY, g.variant->NT,
                  g.variant->elem == 1 ? "int8" : g.variant->elem == 2 ? "int16" : "int32");
@@ -719,6 +802,7 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
     for (int i = 0; i < n; ++i) {
         if ((st = check_params(&p[i])) != RSOS_OK) return fail(st, "surface %d: %s", i, g_last_error.c_str());
         if (p[i].D != p[0].D) return fail(RSOS_E_INVAL, "all surfaces of a batch share one D");
+        if (p[i].flags != p[0].flags) return fail(RSOS_E_INVAL, "all surfaces of a batch share one storage mode");
         if (offsets[i] < 0) return fail(RSOS_E_INVAL, "negative offset");
     }
     // surfaces must not overlap in the pool
@@ -734,6 +818,7 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
     b->p.assign(p, p + n);
     SurfaceGroup &g = b->g;
     g.D = p[0].D;
+    g.packed = (p[0].flags & RSOS_FLAG_PACKED16) != 0;
     g.stream = (hipStream_t)stream;
     long long pool_elems = 0;
     for (int i = 0; i < n; ++i) pool_elems = std::max(pool_elems, offsets[i] + (long long)p[i].L * p[i].L);
@@ -743,8 +828,15 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
     if ((st = g.dev_alloc((void **)&logs, sizeof(long long) * 3 * log_cap * n)) != RSOS_OK) { g.destroy(); delete b; return st; }
     for (int i = 0; i < n; ++i) {
         SurfDev d = {};
-        d.buf[0] = d_pool + offsets[i];
-        d.buf[1] = work + offsets[i];
+        if (g.packed) {
+            // the surface's int32[L^2] of the pool holds both residue buffers
+            d.buf[0] = d_pool + offsets[i];
+            d.buf[1] = (int32_t *)((uint16_t *)(d_pool + offsets[i]) + (size_t)p[i].L * p[i].L);
+            g.readout.push_back(work + offsets[i]);
+        } else {
+            d.buf[0] = d_pool + offsets[i];
+            d.buf[1] = work + offsets[i];
+        }
         d.log = logs + 3 * log_cap * i;
         d.log_cap = log_cap;
         d.key0 = (uint32_t)(p[i].seed & 0xFFFFFFFFu);
@@ -757,14 +849,12 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
         g.t0.push_back(0);
     }
     if ((st = mark(g, g.setup())) != RSOS_OK) { g.destroy(); delete b; return st; }
-    for (int i = 0; i < n; ++i) {
-        hipError_t e = hipMemsetAsync(g.host[i].buf[0], 0, (size_t)p[i].L * p[i].L * 4, g.stream);
-        if (e != hipSuccess) { g.destroy(); delete b; return fail(RSOS_E_DEVICE, "memset: %s", hipGetErrorString(e)); }
-    }
-    hipError_t e = hipStreamSynchronize(g.stream);
-    if (e != hipSuccess) { g.destroy(); delete b; return fail(RSOS_E_DEVICE, "sync: %s", hipGetErrorString(e)); }
     for (int i = 0; i < n; ++i)
-        if ((st = g.init_record(i, 0, 0)) != RSOS_OK) { g.destroy(); delete b; return st; }
+        if ((st = g.load_initial(i, nullptr, 0)) != RSOS_OK || (st = g.init_record(i, 0, 0)) != RSOS_OK) {
+            g.destroy();
+            delete b;
+            return st;
+        }
     *out = b;
     return RSOS_OK;
 }

@@ -15,17 +15,21 @@
 // Kernels:
 //   block_sweep  one workgroup owns a TX x TY tile block of the shifted frame
 //                plus a ring of D+1 sites.  It loads the block and ring from
-//                the input buffer into LDS (aligned 16-byte chunks, int16
-//                offsets from a per-block reference height when N is small
-//                enough), recomputes the phase-0 update of the colour-0 tiles
-//                just outside the block (their inputs are all in the ring,
-//                and the update is a pure function of them), runs phase 1 on
-//                the block, stores the block into the output buffer and adds
-//                its (S1, S2, A) to one of the surface's 64 accumulator
-//                slots.  Both phases of a sweep cost one read and one write
-//                of every site.
+//                the input buffer into LDS (aligned 16-byte chunks, stored
+//                as int8 or int16 offsets from a per-block reference height
+//                when they fit), recomputes the phase-0 update of the
+//                colour-0 tiles just outside the block (their inputs are all
+//                in the ring, and the update is a pure function of them),
+//                runs phase 1 on the block, stores the block into the output
+//                buffer and adds its (S1, S2, A) increments to one of the
+//                surface's 64 accumulator slots.  Both phases of a sweep cost
+//                one read and one write of every site.  int8 blocks whose
+//                range does not fit are queued for a second launch of the
+//                same kernel shape with wider staging.
+//   block_sweep16  the same on heights kept in HBM as 16-bit residues
+//                (half the bytes per sweep) when N L <= 32766.
 //   reduce_acc   folds each surface's accumulators into its per-sweep log,
-//                clears them and advances its time.
+//                clears them, keeps floor(S1 / L^2) and advances its time.
 //   lds_run      a whole small surface (L^2 * 4 bytes fits in LDS) lives in
 //                one workgroup's LDS for many sweeps; no per-sweep launch.
 #pragma once
@@ -74,6 +78,11 @@ __host__ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1
 // lds_run) kernel advances t.
 // ---------------------------------------------------------------------------
 constexpr int kAccSlots = 64;  // per-surface spread of the (S1, S2, A) atomics
+// Per-surface accumulator area: 3 * kAccSlots words of increments, then
+// word kMeanWord = floor(S1 / L^2) of the current time (kept by reduce_acc;
+// the 16-bit storage mode recovers true heights from it).
+constexpr int kMeanWord = 3 * kAccSlots;
+constexpr int kAccWords = 3 * kAccSlots + 4;
 
 // Lattice pointers reach the kernels through descriptors in memory, so the
 // compiler sees generic pointers and would emit flat memory instructions
@@ -82,6 +91,7 @@ constexpr int kAccSlots = 64;  // per-surface spread of the (S1, S2, A) atomics
 // views.
 typedef __attribute__((address_space(1))) int32_t gint32;
 typedef __attribute__((address_space(1))) unsigned long long gu64;
+typedef __attribute__((address_space(1))) long long gi64;
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) v4i gv4i;
 
@@ -103,7 +113,7 @@ __device__ __forceinline__ void store4(gint32 *p, const int4 v)
 struct SurfDev {
     int32_t *buf[2];      // state after t sweeps is in buf[t & 1]
     long long *log;       // 3 * log_cap int64: (S1, S2, A) of time tau at slot tau % log_cap
-    long long *acc;       // 3 * kAccSlots int64 accumulators, zero between sweeps
+    long long *acc;       // kAccWords int64: accumulators (zero between sweeps), mean floor
     long long log_cap;
     long long t;          // sweeps done
     long long t_end;      // run while t < t_end
@@ -129,51 +139,70 @@ struct TileBits {
 
 // Geometry of a TX x TY tile block with its ring of D+1 sites, as staged in
 // LDS: region rows of RW sites stored with pitch RWL elements, shifted right
-// by the alignment pad (0..3) of the region's first column so that every
-// global load is an aligned 16-byte chunk.
-template <int D, int TX, int TY>
+// by the alignment pad (0..CPC-1) of the region's first column so that every
+// global load is an aligned 16-byte chunk of CPC cells (4 int32 or 8 uint16).
+template <int D, int TX, int TY, int CPC = 4>
 struct BlockGeom {
     static constexpr int RING = D + 1;
     static constexpr int RW = TX * D + 2 * RING;
     static constexpr int RH = TY * D + 2 * RING;
-    static constexpr int RWL = (RW + 3 + 3) & ~3;
-    static constexpr int CH = RWL / 4;
+    static constexpr int RWL = (RW + 2 * (CPC - 1)) & ~(CPC - 1);
+    static constexpr int CH = RWL / CPC;
     static constexpr int HALF = TX * TY / 2;
     static constexpr int P0 = HALF + TX + TY;
     static constexpr int BW = TX * D, BH = TY * D;
 };
 
-// D^2 sequential attempts of one tile whose site (u, v) sits at LDS index
-// base + v*P + u (neighbours at +-1 and +-P).  E is the LDS element type:
-// int16 holds heights relative to a per-block reference, int32 raw heights.
-// Adds the accepted count to acc and, over accepted attempts, 2c + 1 (c the
-// staged value before the deposit) to q: a deposit on height h raises
-// sum h^2 by 2h + 1.
+// One attempt on the site at field f of a tile whose site (u, v) sits at LDS
+// index base + v*P + u (neighbours at +-1 and +-P).  E is the LDS element
+// type: narrow types hold heights relative to a per-block base, int32 raw
+// heights.  Adds the acceptance to acc and, when accepted, the staged value
+// c before the deposit to q (a deposit on height h raises sum h^2 by 2h + 1).
+template <int D, int P, typename E, typename Q>
+__device__ __forceinline__ void attempt(E *lds, int base, uint32_t f, int N, int &acc, Q &q)
+{
+    constexpr int LOG2D = TileBits<D>::LOG2D;
+    const int idx = base + (int)(f >> LOG2D) * P + (int)(f & (D - 1));
+    const int c = lds[idx];
+    const int m = min(min((int)lds[idx - 1], (int)lds[idx + 1]), min((int)lds[idx - P], (int)lds[idx + P]));
+    // h_c + 1 - h_j <= N for every neighbour j; the lower side cannot fail
+    // because |h_c - h_j| <= N held before.
+    int ok;
+    if constexpr (sizeof(E) <= 2) {
+        // narrow staging: c - m and N are far inside int range, so the sign
+        // of c - m - N decides
+        ok = (int)((uint32_t)(c - m - N) >> 31);
+        q += __mul24(c, ok);
+    } else {
+        ok = (c - m) < N;
+        q += ok ? (Q)c : (Q)0;
+    }
+    lds[idx] = (E)(c + ok);
+    acc += ok;
+}
+
+// D^2 sequential attempts of one tile: the Philox calls whose fields are
+// all used, then the call that holds the last D^2 mod (fields per call).
 template <int D, int P, typename E, typename Q>
 __device__ __forceinline__ void tile_attempts(E *lds, int base, uint32_t tile_id, uint32_t s,
                                               uint32_t p, int N, uint32_t k0, uint32_t k1,
                                               int &acc, Q &q)
 {
     using TB = TileBits<D>;
+    constexpr int NFULL = (D * D) / TB::PER, TAIL = (D * D) % TB::PER;
+    constexpr uint32_t MASK = (uint32_t)(D * D - 1);
 #pragma unroll 1
-    for (int j = 0; j < TB::NCALL; ++j) {
+    for (int j = 0; j < NFULL; ++j) {
         const u32x4 r = philox4x32_10((uint32_t)j, tile_id, s, p, k0, k1);
 #pragma unroll
-        for (int k = 0; k < TB::PER; ++k) {
-            if (j * TB::PER + k < D * D) {
-                const uint32_t f = (r.v[k / TB::F] >> ((k % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
-                const int idx = base + (int)(f >> TB::LOG2D) * P + (int)(f & (D - 1));
-                const int c = lds[idx];
-                const int m = min(min((int)lds[idx - 1], (int)lds[idx + 1]),
-                                  min((int)lds[idx - P], (int)lds[idx + P]));
-                // h_c + 1 - h_j <= N for every neighbour j; the lower side
-                // cannot fail because |h_c - h_j| <= N held before.
-                const int ok = (c - m) < N;
-                lds[idx] = (E)(c + ok);
-                acc += ok;
-                q += ok ? (Q)2 * (Q)c + (Q)1 : (Q)0;
-            }
-        }
+        for (int k = 0; k < TB::PER; ++k)
+            attempt<D, P, E, Q>(lds, base, (r.v[k / TB::F] >> ((k % TB::F) * TB::B)) & MASK, N, acc, q);
+    }
+    if constexpr (TAIL > 0) {
+        const u32x4 r = philox4x32_10((uint32_t)NFULL, tile_id, s, p, k0, k1);
+#pragma unroll
+        for (int k = 0; k < TAIL; ++k)
+            attempt<D, P, E, Q>(lds, base, (r.v[k / TB::F] >> ((k % TB::F) * TB::B)) & MASK, N, acc, q);
     }
 }
 
@@ -272,17 +301,93 @@ __device__ __forceinline__ void store4_stream(gint32 *dst, const int4 v)
     __builtin_nontemporal_store(x, reinterpret_cast<gv4i *>(dst));
 }
 
+// Descriptor index of the surface that owns global block lb (descriptors
+// are sorted by block_start).
+__device__ __forceinline__ int find_surface(const SurfDev *descs, int nsurf, int lb)
+{
+    int lo = 0, hi = nsurf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].block_start <= lb) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Both phases of one sweep on a block staged in LDS with row pitch RWL and
+// block column 0 at column off of region row RING.  Phase 0: the colour-0
+// tiles of the block, then the colour-0 ring tiles that touch the block's
+// colour-1 border tiles (their counts belong to the neighbouring blocks and
+// are dropped); phase 1: the colour-1 tiles of the block.  acc and q receive
+// this thread's accepted count and sum of accepted staged values.
+template <int D, int TX, int TY, int NT, int RWL, typename E, typename Q>
+__device__ __forceinline__ void block_phases(E *lds, int off, int bx, int by, int T, uint32_t s, int N,
+                                             uint32_t k0, uint32_t k1, int &acc, Q &q)
+{
+    constexpr int RING = D + 1, HALF = TX * TY / 2, P0 = HALF + TX + TY;
+    for (int k = threadIdx.x; k < P0; k += NT) {
+        int ltx, lty;
+        if (k < HALF) {
+            lty = k / (TX / 2);
+            ltx = 2 * (k % (TX / 2)) + (lty & 1);
+        } else {
+            const int g = k - HALF;
+            if (g < TX / 2) { lty = -1; ltx = 2 * g + 1; }
+            else if (g < TX) { lty = TY; ltx = 2 * (g - TX / 2); }
+            else if (g < TX + TY / 2) { ltx = -1; lty = 2 * (g - TX) + 1; }
+            else { ltx = TX; lty = 2 * (g - TX - TY / 2); }
+        }
+        int gtx = bx * TX + ltx, gty = by * TY + lty;
+        gtx = gtx < 0 ? gtx + T : (gtx >= T ? gtx - T : gtx);
+        gty = gty < 0 ? gty + T : (gty >= T ? gty - T : gty);
+        const int base = (lty * D + RING) * RWL + ltx * D + off;
+        int a = 0;
+        Q qq = 0;
+        tile_attempts<D, RWL, E, Q>(lds, base, (uint32_t)(gty * T + gtx), s, 0u, N, k0, k1, a, qq);
+        if (k < HALF) { acc += a; q += qq; }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < HALF; k += NT) {
+        const int lty = k / (TX / 2);
+        const int ltx = 2 * (k % (TX / 2)) + 1 - (lty & 1);
+        const int gtx = bx * TX + ltx, gty = by * TY + lty;
+        const int base = (lty * D + RING) * RWL + ltx * D + off;
+        tile_attempts<D, RWL, E, Q>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1, acc, q);
+    }
+    __syncthreads();
+}
+
+// Adds the block's increments (A, 2 sum(base + c) + A, A) of S1, S2 and
+// the accepted count to one of the surface's accumulator slots (q = sum of
+// the staged values c before the accepted deposits; base is the height that
+// staged value 0 stands for).  Ends with a barrier (LDS is reused by the next
+// queued block).
+template <int NT, typename Q>
+__device__ __forceinline__ void block_commit(const SurfDev &d, int b, int acc, Q q, long long base)
+{
+    long long A = acc, S2inc = (long long)q, unused = 0;
+    block_reduce3<NT>(A, S2inc, unused);
+    if (threadIdx.x == 0) {
+        S2inc = 2ll * S2inc + A + 2ll * base * A;
+        gu64 *a = (gu64 *)(d.acc + 3 * (b & (kAccSlots - 1)));
+        __hip_atomic_fetch_add(a + 0, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a + 1, (unsigned long long)S2inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a + 2, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// block_sweep: one sweep for every active surface of the descriptor table.
+// block_sweep: one sweep for every active surface of the descriptor table,
+// int32 heights in HBM.
 // Requirements checked on the host: T % TX == 0, T % TY == 0, TX and TY
 // even, RWL <= L, RH <= L, 16-byte aligned buffers, and for E = int16
 // N * (RW + RH + 4) + D^2 <= 32767 (every staged value stays within int16
 // of the reference: any two region sites are joined by a path of at most
 // RW + RH - 2 bonds, each of height difference <= N, and no site gains
 // more than D^2 in a sweep).
-// The block's accumulator slot receives (A, 2 ref A + sum(2c+1), A): the
-// sweep's increments of S1 and S2 (exact), from which reduce_acc advances
-// the surface's sums.
+// The block's accumulator slot receives (A, sum(2h+1), A) over its accepted
+// deposits (h the height before the deposit): the sweep's increments of S1
+// and S2 (exact), from which reduce_acc advances the surface's sums.
 // ---------------------------------------------------------------------------
 template <typename E>
 struct StageLimits {
@@ -312,12 +417,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     const int nq = FALLBACK ? queue[0] : 1;
     for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
     const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
-    int lo = 0, hi = nsurf - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].block_start <= lb) lo = mid; else hi = mid - 1;
-    }
-    const SurfDev &d = descs[lo];
+    const SurfDev &d = descs[find_surface(descs, nsurf, lb)];
     const long long t = d.t;
     if (t >= d.t_end) continue;
 
@@ -404,40 +504,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     const int off = G::RING + cpad;  // LDS column of block column 0
     int acc = 0;
     Q q = 0;
-    // ---- phase 0: colour-0 tiles of the block, then the colour-0 ring tiles
-    // that touch the block's colour-1 border tiles (their counts are the
-    // neighbouring blocks' and are dropped here)
-    for (int k = threadIdx.x; k < G::P0; k += NT) {
-        int ltx, lty;
-        if (k < G::HALF) {
-            lty = k / (TX / 2);
-            ltx = 2 * (k % (TX / 2)) + (lty & 1);
-        } else {
-            const int g = k - G::HALF;
-            if (g < TX / 2) { lty = -1; ltx = 2 * g + 1; }
-            else if (g < TX) { lty = TY; ltx = 2 * (g - TX / 2); }
-            else if (g < TX + TY / 2) { ltx = -1; lty = 2 * (g - TX) + 1; }
-            else { ltx = TX; lty = 2 * (g - TX - TY / 2); }
-        }
-        int gtx = bx * TX + ltx, gty = by * TY + lty;
-        gtx = gtx < 0 ? gtx + T : (gtx >= T ? gtx - T : gtx);
-        gty = gty < 0 ? gty + T : (gty >= T ? gty - T : gty);
-        const int base = (lty * D + G::RING) * G::RWL + ltx * D + off;
-        int a = 0;
-        Q qq = 0;
-        tile_attempts<D, G::RWL, E, Q>(lds, base, (uint32_t)(gty * T + gtx), s, 0u, N, k0, k1, a, qq);
-        if (k < G::HALF) { acc += a; q += qq; }
-    }
-    __syncthreads();
-    // ---- phase 1: colour-1 tiles of the block
-    for (int k = threadIdx.x; k < G::HALF; k += NT) {
-        const int lty = k / (TX / 2);
-        const int ltx = 2 * (k % (TX / 2)) + 1 - (lty & 1);
-        const int gtx = bx * TX + ltx, gty = by * TY + lty;
-        const int base = (lty * D + G::RING) * G::RWL + ltx * D + off;
-        tile_attempts<D, G::RWL, E, Q>(lds, base, (uint32_t)(gty * T + gtx), s, 1u, N, k0, k1, acc, q);
-    }
-    __syncthreads();
+    block_phases<D, TX, TY, NT, G::RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
 
     // ---- store the block: aligned 16-byte chunks (LDS and global columns
     // share their alignment), masked single stores in the partial chunks
@@ -459,21 +526,30 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         const int line = (4 * (gxa + 4 * kslot)) & ~127;
         const bool whole_line = (L % 32 == 0) && line >= row_lo && line + 128 <= row_hi &&
                                 gxa + off + G::BW <= L;
-        for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
-            int gy = gy0 + G::RING + r;
-            if (gy >= L) gy -= L;
-            gint32 *row = hout + (size_t)gy * L;
-            const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
-            const int4 v = Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref);
-            if (!partial) {
-                if (whole_line)
-                    store4_stream(row + gc, v);
-                else
+        // (separate loops: the compiler would otherwise merge the two kinds
+        // of store into one plain store)
+        if (whole_line) {
+            for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
+                int gy = gy0 + G::RING + r;
+                if (gy >= L) gy -= L;
+                const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
+                store4_stream(hout + (size_t)gy * L + gc,
+                              Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref));
+            }
+        } else {
+            for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
+                int gy = gy0 + G::RING + r;
+                if (gy >= L) gy -= L;
+                gint32 *row = hout + (size_t)gy * L;
+                const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
+                const int4 v = Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref);
+                if (!partial) {
                     store4(row + gc, v);
-            } else {
-                if (m <= 1) row[gc + 1] = v.y;
-                if (m <= 2) row[gc + 2] = v.z;
-                row[gc + 3] = v.w;
+                } else {
+                    if (m <= 1) row[gc + 1] = v.y;
+                    if (m <= 2) row[gc + 2] = v.z;
+                    row[gc + 3] = v.w;
+                }
             }
         }
         // the trailing partial chunk of each row (cells 0 .. m-1)
@@ -492,23 +568,260 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
             }
         }
     }
-
-    long long A = acc, S2inc = (long long)q, unused = 0;
-    block_reduce3<NT>(A, S2inc, unused);
-    if (threadIdx.x == 0) {
-        S2inc += 2ll * ref * A;
-        gu64 *a = (gu64 *)(d.acc + 3 * (b & (kAccSlots - 1)));
-        __hip_atomic_fetch_add(a + 0, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(a + 1, (unsigned long long)S2inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(a + 2, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_commit<NT>(d, b, acc, q, (long long)ref);
     }
-    __syncthreads();  // LDS is reused by the next queued block
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit storage.  Heights live in HBM as residues mod 2^16.  On the torus
+// the restriction bounds the spread max h - min h by N L (any two sites are
+// joined by a path of at most L bonds), and the mean grows by at most one per
+// sweep, so while N L <= 32766 every height of a sweep lies within 2^15 of
+// m0 = floor(S1 / L^2) at the sweep's start: h = m0 + int16(r - m0 mod 2^16)
+// recovers it from its residue r, and the difference of any two heights is
+// the int16 difference of their residues.  reduce_acc keeps m0 in the
+// accumulator area.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) uint16_t gu16;
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4u gv4u;
+
+// two 16-bit lanes per 32-bit word, each wrapping mod 2^16
+__device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_add16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_max16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_max(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+
+// Staging from 16-bit residues.  uint8 staging holds u = h - (h_ref - 128),
+// checked to lie in [0, 255 - N D] at load time (the same bound as the int8
+// staging of int32 heights); int16 staging holds h - h_ref.
+template <typename E> struct Stage16;
+template <> struct Stage16<uint8_t> {
+    static constexpr int bias = 128;
+    typedef uint2 raw;
+    // 8 lanes of u (two per word) -> 8 bytes; lane maximum into umax
+    __device__ static void put(uint8_t *dst, const v4u w, uint32_t &umax)
+    {
+        umax = pk_max16(umax, pk_max16(pk_max16(w.x, w.y), pk_max16(w.z, w.w)));
+        const uint32_t lo = __builtin_amdgcn_perm(w.y, w.x, 0x06040200u);
+        const uint32_t hi = __builtin_amdgcn_perm(w.w, w.z, 0x06040200u);
+        *reinterpret_cast<uint2 *>(dst) = make_uint2(lo, hi);
+    }
+    // 8 bytes -> 8 residues (bytes spread to the low halves of 16-bit lanes)
+    __device__ static v4u get(const raw r, uint32_t basep)
+    {
+        v4u o;
+        o.x = pk_add16(__builtin_amdgcn_perm(0u, r.x, 0x0C010C00u), basep);
+        o.y = pk_add16(__builtin_amdgcn_perm(0u, r.x, 0x0C030C02u), basep);
+        o.z = pk_add16(__builtin_amdgcn_perm(0u, r.y, 0x0C010C00u), basep);
+        o.w = pk_add16(__builtin_amdgcn_perm(0u, r.y, 0x0C030C02u), basep);
+        return o;
+    }
+};
+template <> struct Stage16<int16_t> {
+    static constexpr int bias = 0;
+    typedef uint4 raw;
+    __device__ static void put(int16_t *dst, const v4u w, uint32_t &)
+    {
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(w.x, w.y, w.z, w.w);
+    }
+    __device__ static v4u get(const raw r, uint32_t basep)
+    {
+        v4u o;
+        o.x = pk_add16(r.x, basep);
+        o.y = pk_add16(r.y, basep);
+        o.z = pk_add16(r.z, basep);
+        o.w = pk_add16(r.w, basep);
+        return o;
+    }
+};
+
+// block_sweep16: block_sweep on 16-bit residues.  E = uint8 (checked; the
+// blocks that do not fit are queued) or int16 (FALLBACK: walks the queue).
+// Host requirements as for block_sweep, with chunks of 8 cells: L % 8 == 0,
+// RWL <= L, N L <= 32766, N D <= 96, and N (RW + RH + 4) + D^2 <= 32767 for
+// the int16 fallback.
+template <int D, int TX, int TY, int NT, typename E, bool FALLBACK>
+__global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ descs, int nsurf,
+                                                    int *__restrict__ queue)
+{
+    using G = BlockGeom<D, TX, TY, 8>;
+    using S = Stage16<E>;
+    constexpr bool checked = sizeof(E) == 1;
+    __shared__ __attribute__((aligned(16))) E lds[G::RWL * G::RH];
+    __shared__ int s_bad;
+
+    if (checked) {
+        if (threadIdx.x == 0) s_bad = 0;
+        __syncthreads();
+    }
+    const int nq = FALLBACK ? queue[0] : 1;
+    for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
+    const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
+    const SurfDev &d = descs[find_surface(descs, nsurf, lb)];
+    const long long t = d.t;
+    if (t >= d.t_end) continue;
+
+    const int L = d.L, N = d.N, T = d.T;
+    const uint32_t s = (uint32_t)t;
+    const uint32_t k0 = d.key0, k1 = d.key1;
+    const gu16 *__restrict__ hin = (const gu16 *)d.buf[t & 1];
+    gu16 *__restrict__ hout = (gu16 *)d.buf[(t + 1) & 1];
+
+    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
+    const int ox = (int)(org.v[0] % (2u * D));
+    const int oy = (int)(org.v[1] % (2u * D));
+
+    const int b = lb - d.block_start;
+    const int bx = b % d.nbx, by = b / d.nbx;
+    int gx0 = ox + bx * TX * D - G::RING;
+    int gy0 = oy + by * TY * D - G::RING;
+    if (gx0 < 0) gx0 += L;
+    if (gy0 < 0) gy0 += L;
+    const int cpad = gx0 & 7;
+    const int gxa = gx0 - cpad;  // LDS column c holds global column gxa + c (mod L)
+    const uint32_t ref_r = hin[(size_t)gy0 * L + gx0];
+    const uint32_t base_r = (ref_r - S::bias) & 0xFFFFu;  // residue of staged value 0
+    const uint32_t basep = base_r * 0x10001u;
+
+    uint32_t umax = 0;
+    {
+        constexpr int NCH = G::CH * G::RH;
+        constexpr int U = 8;
+        constexpr int FULL = NCH / (NT * U);
+        auto fetch = [&](int i) {
+            const int r = i / G::CH, cc = i - r * G::CH;
+            int gy = gy0 + r;
+            if (gy >= L) gy -= L;
+            int gx = gxa + 8 * cc;
+            if (gx >= L) gx -= L;
+            return *reinterpret_cast<const gv4u *>(hin + (size_t)gy * L + gx);
+        };
+        auto stage = [&](int i, const v4u &v) {
+            const int r = i / G::CH, cc = i - r * G::CH;
+            v4u w;
+            w.x = pk_sub16(v.x, basep);
+            w.y = pk_sub16(v.y, basep);
+            w.z = pk_sub16(v.z, basep);
+            w.w = pk_sub16(v.w, basep);
+            S::put(lds + r * G::RWL + 8 * cc, w, umax);
+        };
+#pragma unroll 1
+        for (int g = 0; g < FULL; ++g) {
+            const int i0 = g * NT * U + threadIdx.x;
+            v4u v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = fetch(i0 + u * NT);
+#pragma unroll
+            for (int u = 0; u < U; ++u) stage(i0 + u * NT, v[u]);
+        }
+        {
+            const int i0 = FULL * NT * U + threadIdx.x;
+            v4u v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u * NT < NCH) v[u] = fetch(i0 + u * NT);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u * NT < NCH) stage(i0 + u * NT, v[u]);
+        }
+    }
+    if (checked) {
+        // u = h - h_ref + 128 must lie in [0, 255 - N D] (see block_sweep);
+        // |h - h_ref| < 2^15, so an out-of-range u shows as a 16-bit lane
+        // above 255 - N D
+        if ((int)max(umax & 0xFFFFu, umax >> 16) > 255 - N * D) s_bad = 1;
+    }
+    __syncthreads();
+    if (checked && s_bad) {
+        if (threadIdx.x == 0) {
+            const int k = atomicAdd(queue, 1);
+            queue[1 + k] = lb;
+        }
+        continue;
+    }
+
+    const int off = G::RING + cpad;
+    int acc = 0;
+    int q = 0;
+    block_phases<D, TX, TY, NT, G::RWL, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+
+    // ---- store: 16-byte chunks of 8 residues; 16-bit stores in the partial
+    // chunks at both ends of each row
+    {
+        constexpr int SPR = G::BW / 8;
+        static_assert(NT % SPR == 0, "threads must tile whole block rows");
+        constexpr int RPP = NT / SPR;
+        const int m = off & 7;
+        const int slot = threadIdx.x % SPR;
+        const int kslot = (off >> 3) + slot;
+        int gc = gxa + 8 * kslot;
+        if (gc >= L) gc -= L;
+        const bool partial = slot == 0 && m != 0;
+        // byte offsets within the row; rows are 128-byte aligned when L % 64 == 0
+        const int row_lo = 2 * (gxa + off), row_hi = row_lo + 2 * G::BW;
+        const int line = (2 * (gxa + 8 * kslot)) & ~127;
+        const bool whole_line = (L % 64 == 0) && line >= row_lo && line + 128 <= row_hi &&
+                                gxa + off + G::BW <= L;
+        if (whole_line) {
+            for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
+                int gy = gy0 + G::RING + r;
+                if (gy >= L) gy -= L;
+                const E *src = lds + (G::RING + r) * G::RWL + 8 * kslot;
+                __builtin_nontemporal_store(S::get(*reinterpret_cast<const typename S::raw *>(src), basep),
+                                            reinterpret_cast<gv4u *>(hout + (size_t)gy * L + gc));
+            }
+        } else {
+            for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
+                int gy = gy0 + G::RING + r;
+                if (gy >= L) gy -= L;
+                gu16 *row = hout + (size_t)gy * L;
+                const E *src = lds + (G::RING + r) * G::RWL + 8 * kslot;
+                if (!partial) {
+                    *reinterpret_cast<gv4u *>(row + gc) = S::get(*reinterpret_cast<const typename S::raw *>(src), basep);
+                } else {
+#pragma unroll
+                    for (int k = 1; k < 8; ++k)
+                        if (k >= m) row[gc + k] = (uint16_t)(base_r + (uint32_t)(int)src[k]);
+                }
+            }
+        }
+        if (m != 0) {
+            const int kt = (off >> 3) + SPR;
+            int gct = gxa + 8 * kt;
+            if (gct >= L) gct -= L;
+            for (int r = threadIdx.x; r < G::BH; r += NT) {
+                int gy = gy0 + G::RING + r;
+                if (gy >= L) gy -= L;
+                gu16 *row = hout + (size_t)gy * L;
+                const E *src = lds + (G::RING + r) * G::RWL + 8 * kt;
+#pragma unroll
+                for (int k = 0; k < 7; ++k)
+                    if (k < m) row[gct + k] = (uint16_t)(base_r + (uint32_t)(int)src[k]);
+            }
+        }
+    }
+    // true height of staged value 0
+    const long long m0 = *(const gi64 *)(d.acc + kMeanWord);
+    const long long href = m0 + (long long)(int16_t)(uint16_t)(ref_r - (uint32_t)m0);
+    block_commit<NT>(d, b, acc, q, href - S::bias);
     }
 }
 
 // Folds each active surface's accumulated increments into its log (the
-// record of t+1 is the record of t plus the increments), clears them and
-// advances t.  One 64-thread workgroup per surface.
+// record of t+1 is the record of t plus the increments), clears them,
+// updates the floor of the mean height and advances t.  One 64-thread
+// workgroup per surface.
 __global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs, int *__restrict__ queue)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0;
@@ -528,8 +841,25 @@ __global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs, in
         e[0] = s1;
         e[1] = s2;
         e[2] = z;
+        d.acc[kMeanWord] = s1 / ((long long)d.L * d.L);
         d.t = t + 1;
     }
+}
+
+// Conversions between int32 heights and 16-bit residues (grid-stride).
+__global__ void pack16(const int32_t *__restrict__ src, uint16_t *__restrict__ dst, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (uint16_t)(uint32_t)src[i];
+}
+
+__global__ void unpack16(const uint16_t *__restrict__ src, int32_t *__restrict__ dst, long long n,
+                         const long long *__restrict__ mean_floor)
+{
+    const long long m0 = *mean_floor;
+    const uint32_t r0 = (uint32_t)m0 & 0xFFFFu;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (int32_t)(m0 + (long long)(int16_t)(uint16_t)((uint32_t)src[i] - r0));
 }
 
 // ---------------------------------------------------------------------------

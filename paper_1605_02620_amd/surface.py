@@ -29,8 +29,9 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _params(L, N, D, seed):
-    return Params(int(L), int(N), int(D), 0, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)).value)
+def _params(L, N, D, seed, packed=False):
+    flags = _lib.FLAG_PACKED16 if packed else 0
+    return Params(int(L), int(N), int(D), flags, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)).value)
 
 
 def _widths(buf, n):
@@ -39,17 +40,24 @@ def _widths(buf, n):
 
 
 class Surface:
-    """One L x L surface (rsos_init / rsos_sweep / rsos_width)."""
+    """One L x L surface (rsos_init / rsos_sweep / rsos_width).
+
+    packed=True keeps the heights as 16-bit residues in device memory
+    (RSOS_FLAG_PACKED16; N*L <= 32766): identical results, half the bytes
+    per sweep.  The two int32[L*L] tensors are then the residue pair and
+    the int32 readout scratch."""
 
     def __init__(self, L: int, N: int = 1, seed: int = 0, D: int = 8, h0=None, t0: int = 0,
-                 log_cap: int = 0, device="cuda", stream=None):
+                 log_cap: int = 0, device="cuda", stream=None, packed: bool = False):
         dev = _require_gpu(device)
         self.L, self.N, self.D, self.seed = int(L), int(N), int(D), int(seed)
+        self.packed = bool(packed)
+        self.device = dev
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         n = self.L * self.L
         self.bufs = (torch.empty(n, dtype=torch.int32, device=dev),
                      torch.empty(n, dtype=torch.int32, device=dev))
-        p = _params(L, N, D, seed)
+        p = _params(L, N, D, seed, self.packed)
         h0p = None
         if h0 is not None:
             self._h0 = np.ascontiguousarray(np.asarray(h0, dtype=np.int32).reshape(-1))
@@ -87,8 +95,13 @@ class Surface:
         return out
 
     def heights_tensor(self) -> torch.Tensor:
-        """The current state as a device tensor (a view of one of the buffers)."""
-        return self.bufs[self.time() & 1]
+        """The current state as an int32 device tensor: a view of one of the
+        buffers, or (packed) a new tensor the library converts into."""
+        if not self.packed:
+            return self.bufs[self.time() & 1]
+        out = torch.empty(self.L * self.L, dtype=torch.int32, device=self.device)
+        check(lib().rsos_heights(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
 
     def kernel_name(self) -> str:
         buf = ctypes.create_string_buffer(128)
@@ -123,10 +136,12 @@ class Batch:
 
     ALIGN = 64  # elements (256 bytes) between surfaces in the pool
 
-    def __init__(self, specs, D: int = 8, log_cap: int = 0, device="cuda", stream=None):
+    def __init__(self, specs, D: int = 8, log_cap: int = 0, device="cuda", stream=None,
+                 packed: bool = False):
         dev = _require_gpu(device)
         self.specs = [(int(L), int(N), int(seed)) for (L, N, seed) in specs]
         self.D = int(D)
+        self.packed = bool(packed)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         offs, off = [], 0
         for (L, _, _) in self.specs:
@@ -135,7 +150,7 @@ class Batch:
         self.offsets = np.asarray(offs, dtype=np.int64)
         self.pool = torch.empty(max(off, 1), dtype=torch.int32, device=dev)
         self.work = torch.empty(max(off, 1), dtype=torch.int32, device=dev)
-        ps = (Params * len(self.specs))(*[_params(L, N, D, s) for (L, N, s) in self.specs])
+        ps = (Params * len(self.specs))(*[_params(L, N, D, s, self.packed) for (L, N, s) in self.specs])
         self._h = ctypes.c_void_p()
         check(lib().rsos_batch_init(ctypes.byref(self._h), len(self.specs), ps,
                                     ctypes.c_void_p(self.pool.data_ptr()),

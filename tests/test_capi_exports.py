@@ -88,3 +88,31 @@ def test_status_strings(so):
     from paper_1605_02620_amd import _lib
     for st in range(-7, 1):
         assert _lib.lib().rsos_strerror(st)
+
+
+def test_parameter_checks_without_gpu(so):
+    """rsos_init validates its parameters on the host before any device call:
+    unknown flags, and the limits of the 16-bit storage mode (N*L <= 32766,
+    the tile-block path, N*D <= 96)."""
+    from paper_1605_02620_amd import _lib
+    lib = _lib.lib()
+
+    def init(L, N, D, flags):
+        p = _lib.Params(L, N, D, flags, 1)
+        h = ctypes.c_void_p()
+        st = lib.rsos_init(ctypes.byref(h), ctypes.byref(p), None, None, None, 0, 0, None)
+        return st, lib.rsos_last_error().decode()
+
+    assert init(1024, 1, 8, 2)[0] == _lib.E_INVAL
+    assert "flags" in init(1024, 1, 8, 2)[1]
+    st, msg = init(16384, 2, 8, _lib.FLAG_PACKED16)          # N L = 32768
+    assert st == _lib.E_INVAL and "32766" in msg
+    st, msg = init(64, 1, 8, _lib.FLAG_PACKED16)             # LDS-path size
+    assert st == _lib.E_INVAL and "LDS" in msg
+    st, msg = init(1024, 13, 8, _lib.FLAG_PACKED16)          # N D = 104 > 96
+    assert st == _lib.E_INVAL and "tile-block" in msg
+    # valid parameters get as far as the NULL buffer check
+    for (L, N, D) in [(16384, 1, 8), (8192, 3, 8), (4096, 7, 8), (1024, 12, 8), (256, 1, 8), (512, 3, 16),
+                      (256, 1, 2), (256, 2, 4)]:
+        st, msg = init(L, N, D, _lib.FLAG_PACKED16)
+        assert st == _lib.E_INVAL and "d_h" in msg, (L, N, D, msg)
