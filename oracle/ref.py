@@ -55,6 +55,7 @@ def lib():
         L.ref_rsos_holds.argtypes = [_i32p, ctypes.c_int, ctypes.c_int]
         L.ref_rsos_holds.restype = ctypes.c_int
         L.ref_sums.argtypes = [_i32p, ctypes.c_int, _i64p, _i64p]
+        L.ref_power_sums.argtypes = [_i32p, ctypes.c_int, ctypes.c_int64, _i64p]
         L.ref_run.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                               ctypes.c_int64, ctypes.c_int64, _i64p]
         L.ref_run.restype = ctypes.c_int
@@ -177,6 +178,41 @@ def sums(h, L):
     a, b = ctypes.c_int64(), ctypes.c_int64()
     lib().ref_sums(_p32(h), L, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
+
+
+def power_sums(h, L, R):
+    """C_k = sum (h - R)^k, k = 1..4, exact (Python ints)."""
+    out = np.zeros(8, dtype=np.int64)
+    lib().ref_power_sums(_p32(h), L, int(R), _p64(out))
+    vals = []
+    for k in range(4):
+        lo, hi = int(out[2 * k]) & (2 ** 64 - 1), int(out[2 * k + 1])
+        vals.append((hi << 64) | lo)
+    return vals
+
+
+def central_moments(n, R, c):
+    """Exact central moments Phi_2..Phi_4 of a distribution of n integer
+    values (Eqs. (13)-(15), sums over the sites of one surface) from the
+    power sums c = (C_1..C_4) about R: with d = mean - R = C_1/n, the binomial
+    expansion of (h - R - d)^k."""
+    n = int(n)
+    m = [Fraction(1)] + [Fraction(int(ck), n) for ck in c]   # raw moments about R
+    d = m[1]
+    phi2 = m[2] - d * d
+    phi3 = m[3] - 3 * d * m[2] + 2 * d ** 3
+    phi4 = m[4] - 4 * d * m[3] + 6 * d * d * m[2] - 3 * d ** 4
+    return phi2, phi3, phi4
+
+
+def moments(h, L):
+    """Height-distribution moments of one surface: reference R = floor(mean),
+    power sums about R, exact central moments (Fractions)."""
+    s1, _ = sums(h, L)
+    n = int(L) * int(L)
+    R = s1 // n
+    c = power_sums(h, L, R)
+    return {"ref": R, "c": c, "phi": central_moments(n, R, c)}
 
 
 def width2(L, s1, s2):

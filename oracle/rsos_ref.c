@@ -163,6 +163,24 @@ void ref_sums(const int32_t *h, int L, int64_t *s1, int64_t *s2)
     *s2 = b;
 }
 
+void ref_power_sums(const int32_t *h, int L, int64_t R, int64_t out[8])
+{
+    __int128 c[4] = {0, 0, 0, 0};
+    for (int64_t i = 0; i < (int64_t)L * L; ++i) {
+        const __int128 x = (__int128)h[i] - R;
+        __int128 p = x;
+        for (int k = 0; k < 4; ++k) {
+            c[k] += p;
+            p *= x;
+        }
+    }
+    for (int k = 0; k < 4; ++k) {
+        const unsigned __int128 u = (unsigned __int128)c[k];
+        out[2 * k] = (int64_t)(uint64_t)u;
+        out[2 * k + 1] = (int64_t)(uint64_t)(u >> 64);
+    }
+}
+
 static int check_args(int L, int N, int D)
 {
     if (!valid_D(D) || L <= 0 || N < 1) return -1;

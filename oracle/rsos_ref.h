@@ -68,6 +68,12 @@ int ref_rsos_holds(const int32_t *h, int L, int N);
 /* Sum h and sum h^2 over the lattice, in int64. */
 void ref_sums(const int32_t *h, int L, int64_t *s1, int64_t *s2);
 
+/* Power sums about an integer reference R for the height-distribution
+ * moments of Eqs. (13)-(15): C_k = sum over sites of (h - R)^k, k = 1..4,
+ * accumulated exactly in 128-bit integers.  out[2k-2], out[2k-1] receive the
+ * low and high 64-bit halves of C_k (two's complement). */
+void ref_power_sums(const int32_t *h, int L, int64_t R, int64_t out[8]);
+
 /* Tile-checkerboard sweeps s = t0 .. t0+n-1 in place.  log (may be NULL)
  * receives 4 int64 per sweep: (t = s+1, S1, S2, A). */
 int ref_run(int32_t *h, int L, int N, int D, uint64_t seed, int64_t t0, int64_t n,
