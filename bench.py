@@ -20,7 +20,9 @@ Printed JSON line (one): attempts per ns over the timed region, plus
                 engine: p50/p99 latency from arrival and aggregate rate;
   packed16      the same surface and sweeps with heights kept on the device
                 as 16-bit residues (identical results, 4 B per attempt), with
-                its own roofline.
+                its own roofline;
+  moments       time of one exact height-distribution moment call on the
+                final state (one read of the lattice).
 --storage packed16 makes the 16-bit surface the headline (for profiling it
 alone).
 """
@@ -111,6 +113,13 @@ def bench_single(L, N, D, seed, steps, warmup, packed=False):
     s.timing(False)
     w = s.width()
     kname = s.kernel_name()
+    # height-distribution moments of the final state (one read of the
+    # lattice per call, synchronous)
+    s.moments()
+    t1 = time.perf_counter()
+    for _ in range(10):
+        mom = s.moments()
+    mom_ms = (time.perf_counter() - t1) * 1e3 / 10
     s.close()
     bpa = BYTES_PER_ATTEMPT // 2 if packed else BYTES_PER_ATTEMPT
     achieved = L * L * bpa / (mean_ms * 1e-3) / 1e9
@@ -119,7 +128,10 @@ def bench_single(L, N, D, seed, steps, warmup, packed=False):
                 "traffic": _traffic(kname, packed), "traffic_unit": "bytes per launch",
                 "kernel": kname, "launches_timed": launches, "kernel_mean_ms": round(mean_ms, 4),
                 "algorithmic_bytes_per_launch": L * L * bpa}
-    return {"value": value, "dt": dt, "w": w, "roofline": roofline}
+    moments = {"ms_per_call": round(mom_ms, 4),
+               "GBps_read": round(L * L * (bpa // 2) / (mom_ms * 1e-3) / 1e9, 1),
+               "phi2": mom["phi2"], "phi3": mom["phi3"], "phi4": mom["phi4"]}
+    return {"value": value, "dt": dt, "w": w, "roofline": roofline, "moments": moments}
 
 
 def bench_batched(n_steps_batch=200):
@@ -225,7 +237,7 @@ def main():
                       "L": L, "N": N, "D": D, "seed": seed, "sweeps": args.steps,
                       "storage": args.storage,
                       "final_t": int(w["t"]), "final_w2": float(w["w2"])},
-           "roofline": roofline}
+           "roofline": roofline, "moments": head["moments"]}
     if args.storage == "int32" and not args.no_packed:
         # the same surface and sweeps with heights kept as 16-bit residues
         # (identical results; 4 B per attempt)
@@ -234,7 +246,7 @@ def main():
                            "ms_per_step": round(pk["dt"] * 1e3 / args.steps, 4),
                            "final_t": int(pk["w"]["t"]), "final_w2": float(pk["w"]["w2"]),
                            "same_result": bool(pk["w"]["s1"] == w["s1"] and pk["w"]["s2"] == w["s2"]),
-                           "roofline": pk["roofline"]}
+                           "roofline": pk["roofline"], "moments": pk["moments"]}
     if args.copy_probe:
         src = torch.ones(L * L, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

@@ -102,6 +102,27 @@ typedef struct {
     double w2;
 } rsos_width_t;
 
+/* Moments of the height distribution of one state (the moments of Eqs.
+ * (13)-(15) whose averages over samples give the skewness S_h and kurtosis
+ * Q_h of the heights).  Exact power sums about the integer reference
+ * ref = floor(S1 / L^2):
+ *   c1 = sum (h - ref), c2 = sum (h - ref)^2,
+ *   c3 = sum (h - ref)^3, c4 = sum (h - ref)^4 as 128-bit two's complement
+ *   integers, [0] the low 64 bits, [1] the high 64 bits;
+ * and the central moments per site (about the mean S1 / L^2)
+ *   phi2 = W^2, phi3, phi4, evaluated from the exact sums in long double. */
+typedef struct {
+    int64_t t;
+    int64_t ref;
+    int64_t c1;
+    int64_t c2;
+    uint64_t c3[2];
+    uint64_t c4[2];
+    double phi2;
+    double phi3;
+    double phi4;
+} rsos_moments_t;
+
 typedef struct rsos_surface rsos_surface;
 typedef struct rsos_batch rsos_batch;
 typedef struct rsos_engine rsos_engine;
@@ -141,6 +162,11 @@ rsos_status rsos_log(rsos_surface *s, int64_t t_from, int64_t n, rsos_width_t *o
 /* Synchronises and copies the current heights (int32[L*L]) to dst, host or
  * device memory as dst_is_device says. */
 rsos_status rsos_heights(rsos_surface *s, int32_t *dst, int dst_is_device);
+
+/* Synchronises and computes the height-distribution moments of the current
+ * state on the device (one read of the lattice: two kernels on the
+ * surface's stream).  Exact for every state the library accepts. */
+rsos_status rsos_moments(rsos_surface *s, rsos_moments_t *out);
 
 /* Current time t and the device buffer that holds the current int32 state
  * (NULL with RSOS_FLAG_PACKED16). */
@@ -187,6 +213,9 @@ rsos_status rsos_batch_width(rsos_batch *b, rsos_width_t *out);
 
 /* Synchronises; per-sweep records of surface i, as rsos_log. */
 rsos_status rsos_batch_log(rsos_batch *b, int32_t i, int64_t t_from, int64_t n, rsos_width_t *out);
+
+/* Synchronises; height-distribution moments of surface i, as rsos_moments. */
+rsos_status rsos_batch_moments(rsos_batch *b, int32_t i, rsos_moments_t *out);
 
 /* Synchronises; copies surface i's current heights. */
 rsos_status rsos_batch_heights(rsos_batch *b, int32_t i, int32_t *dst, int dst_is_device);

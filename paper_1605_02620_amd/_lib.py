@@ -34,6 +34,19 @@ class Width(ctypes.Structure):
     _fields_ = [("t", c_i64), ("s1", c_i64), ("s2", c_i64), ("accepted", c_i64), ("w2", ctypes.c_double)]
 
 
+class Moments(ctypes.Structure):
+    _fields_ = [("t", c_i64), ("ref", c_i64), ("c1", c_i64), ("c2", c_i64), ("c3", c_u64 * 2),
+                ("c4", c_u64 * 2), ("phi2", ctypes.c_double), ("phi3", ctypes.c_double),
+                ("phi4", ctypes.c_double)]
+
+    def as_dict(self):
+        def i128(a):
+            v = (int(a[1]) << 64) | int(a[0])
+            return v - (1 << 128) if v >> 127 else v
+        return {"t": self.t, "ref": self.ref, "c1": self.c1, "c2": self.c2, "c3": i128(self.c3),
+                "c4": i128(self.c4), "phi2": self.phi2, "phi3": self.phi3, "phi4": self.phi4}
+
+
 class RsosError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"rsos status {status}: {msg}")
@@ -47,6 +60,7 @@ SIGNATURES = [
     ("rsos_width", c_i32, [c_vp, P(Width)]),
     ("rsos_log", c_i32, [c_vp, c_i64, c_i64, P(Width)]),
     ("rsos_heights", c_i32, [c_vp, c_vp, ctypes.c_int]),
+    ("rsos_moments", c_i32, [c_vp, P(Moments)]),
     ("rsos_time", c_i32, [c_vp, P(c_i64), P(c_vp)]),
     ("rsos_timing", c_i32, [c_vp, ctypes.c_int]),
     ("rsos_timing_read", c_i32, [c_vp, P(c_i64), P(ctypes.c_double), P(ctypes.c_double)]),
@@ -56,6 +70,7 @@ SIGNATURES = [
     ("rsos_batch_sweep", c_i32, [c_vp, P(c_i64), c_i64]),
     ("rsos_batch_width", c_i32, [c_vp, P(Width)]),
     ("rsos_batch_log", c_i32, [c_vp, c_i32, c_i64, c_i64, P(Width)]),
+    ("rsos_batch_moments", c_i32, [c_vp, c_i32, P(Moments)]),
     ("rsos_batch_heights", c_i32, [c_vp, c_i32, c_vp, ctypes.c_int]),
     ("rsos_batch_free", c_i32, [c_vp]),
     ("rsos_engine_create", c_i32, [P(c_vp), c_vp, c_i64, c_i32, c_i32, c_vp]),

@@ -7,6 +7,7 @@
 // their sweeps in one lds_run launch instead.
 #include "rsos.h"
 #include "rsos_kernels.hpp"
+#include "rsos_moments.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -46,6 +47,7 @@ rsos_status fail(rsos_status st, const char *fmt, ...)
 constexpr int kLdsMaxBytes = 64 * 1024;  // lds_run: whole surface in LDS
 constexpr int kGraphSweeps = 32;
 constexpr int kFallbackGrid = 256;  // workgroups walking the fallback queue
+constexpr int kPsGrid = 2048;       // workgroups of the power-sum reduction
 
 // ---------------------------------------------------------------------------
 // Block-kernel variants.  The tile block shape never changes results; it
@@ -290,6 +292,7 @@ struct SurfaceGroup {
     SurfDev *d_desc = nullptr;
     long long *d_acc = nullptr;        // kAccWords per block-path surface
     std::vector<int32_t *> readout;    // 16-bit storage: int32[L^2] device scratch per surface
+    long long *d_ps = nullptr;         // power sums: per-workgroup partials, then the result
     int *d_queue = nullptr;            // blocks handed to the wider fallback launch
     std::vector<int> lds_idx, blk_idx; // surfaces on each path
     int *d_lds_idx = nullptr;
@@ -550,6 +553,52 @@ struct SurfaceGroup {
 
     static unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 8192); }
 
+    // Exact power sums of surface i's current heights about floor(S1/L^2)
+    // (rsosk::power_sums_partial / power_sums_final), then the central
+    // moments from them.
+    rsos_status moments(int i, rsos_moments_t *out)
+    {
+        const SurfDev &s = host[i];
+        const long long n = (long long)s.L * s.L;
+        // at most 2^16 sites per thread: grid >= n / 2^24
+        const int grid = (int)std::min<long long>(kPsGrid, std::max<long long>(1, n / (256 * 64)));
+        rsos_status st;
+        if (!d_ps && (st = dev_alloc((void **)&d_ps, sizeof(long long) * (8 * (size_t)kPsGrid + 8))) != RSOS_OK)
+            return st;
+        const long long *rec = s.log + 3 * (s.t % s.log_cap);
+        if (packed)
+            hipLaunchKernelGGL(rsosk::power_sums_partial<uint16_t>, dim3(grid), dim3(256), 0, stream,
+                               (const uint16_t *)s.buf[s.t & 1], n, rec, d_ps);
+        else
+            hipLaunchKernelGGL(rsosk::power_sums_partial<int32_t>, dim3(grid), dim3(256), 0, stream,
+                               (const int32_t *)s.buf[s.t & 1], n, rec, d_ps);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(rsosk::power_sums_final, dim3(1), dim3(256), 0, stream, d_ps, grid,
+                           d_ps + 8 * (size_t)kPsGrid);
+        HIP_TRY(hipGetLastError());
+        rsos_width_t w;
+        if ((st = read_log(i, s.t, 1, &w)) != RSOS_OK) return st;  // synchronises
+        unsigned long long r[8];
+        HIP_TRY(hipMemcpy(r, d_ps + 8 * (size_t)kPsGrid, sizeof r, hipMemcpyDeviceToHost));
+        __int128 c[4];
+        for (int k = 0; k < 4; ++k) c[k] = (__int128)(((unsigned __int128)r[2 * k + 1] << 64) | r[2 * k]);
+        out->t = s.t;
+        out->ref = w.s1 / n;
+        out->c1 = (int64_t)c[0];
+        out->c2 = (int64_t)c[1];
+        out->c3[0] = r[4];
+        out->c3[1] = r[5];
+        out->c4[0] = r[6];
+        out->c4[1] = r[7];
+        // central moments: with d = c1/n in [0, 1), expand (h - ref - d)^k
+        const long double N_ = (long double)n, d = (long double)c[0] / N_;
+        const long double m2 = (long double)c[1] / N_, m3 = (long double)c[2] / N_, m4 = (long double)c[3] / N_;
+        out->phi2 = (double)(m2 - d * d);
+        out->phi3 = (double)(m3 - 3 * d * m2 + 2 * d * d * d);
+        out->phi4 = (double)(m4 - 4 * d * m3 + 6 * d * d * m2 - 3 * d * d * d * d);
+        return RSOS_OK;
+    }
+
     // Writes the initial log record (time t0) of surface i.
     rsos_status init_record(int i, long long s1, long long s2)
     {
@@ -739,6 +788,13 @@ rsos_status rsos_heights(rsos_surface *s, int32_t *dst, int dst_is_device)
     return mark(s->g, s->g.copy_heights(0, dst, dst_is_device));
 }
 
+rsos_status rsos_moments(rsos_surface *s, rsos_moments_t *out)
+{
+    CHECK_HANDLE(s, s->g);
+    if (!out) return fail(RSOS_E_INVAL, "out is NULL");
+    return mark(s->g, s->g.moments(0, out));
+}
+
 rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current)
 {
     CHECK_HANDLE(s, s->g);
@@ -900,6 +956,14 @@ rsos_status rsos_batch_log(rsos_batch *b, int32_t i, int64_t t_from, int64_t n, 
     if (i < 0 || i >= (int)b->g.host.size()) return fail(RSOS_E_INVAL, "surface index out of range");
     if (!out && n > 0) return fail(RSOS_E_INVAL, "out is NULL");
     return mark(b->g, b->g.read_log(i, t_from, n, out));
+}
+
+rsos_status rsos_batch_moments(rsos_batch *b, int32_t i, rsos_moments_t *out)
+{
+    CHECK_HANDLE(b, b->g);
+    if (i < 0 || i >= (int)b->g.host.size()) return fail(RSOS_E_INVAL, "surface index out of range");
+    if (!out) return fail(RSOS_E_INVAL, "out is NULL");
+    return mark(b->g, b->g.moments(i, out));
 }
 
 rsos_status rsos_batch_heights(rsos_batch *b, int32_t i, int32_t *dst, int dst_is_device)

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Params, Width, check, lib
+from ._lib import Moments, Params, Width, check, lib
 
 LOG_DTYPE = np.dtype([("t", np.int64), ("s1", np.int64), ("s2", np.int64),
                       ("accepted", np.int64), ("w2", np.float64)])
@@ -93,6 +93,14 @@ class Surface:
         out = np.empty(self.L * self.L, dtype=np.int32)
         check(lib().rsos_heights(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
         return out
+
+    def moments(self) -> dict:
+        """Height-distribution moments of the current state (rsos_moments):
+        exact power sums c1..c4 about ref = floor(mean), central moments
+        phi2..phi4."""
+        m = Moments()
+        check(lib().rsos_moments(self._h, ctypes.byref(m)))
+        return m.as_dict()
 
     def heights_tensor(self) -> torch.Tensor:
         """The current state as an int32 device tensor: a view of one of the
@@ -179,6 +187,11 @@ class Batch:
         buf = (Width * max(int(n), 1))()
         check(lib().rsos_batch_log(self._h, int(i), int(t_from), int(n), buf))
         return _widths(buf, int(n))
+
+    def moments(self, i: int) -> dict:
+        m = Moments()
+        check(lib().rsos_batch_moments(self._h, int(i), ctypes.byref(m)))
+        return m.as_dict()
 
     def heights(self, i: int) -> np.ndarray:
         L = self.specs[i][0]
