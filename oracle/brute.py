@@ -112,6 +112,63 @@ def _tc_sweep_codes(codes, probs, L, N, D):
     return _merge(np.concatenate(outc), np.concatenate(outp))
 
 
+def _dt_sweep_codes(codes, probs, L, N, D):
+    T = L // D
+    shifts = [(ox, oy) for oy in range(2 * D) for ox in range(2 * D)]
+    outc, outp = [], []
+    for (ox, oy) in shifts:
+        c, pr = codes, probs
+        for k in range(4):
+            for sy in range(T):
+                for sx in range(T):
+                    if (sx % 2) + 2 * (sy % 2) != k:
+                        continue
+                    cells = [((ox + sx * D + u) % L, (oy + sy * D + v) % L)
+                             for v in range(D) for u in range(D)]
+                    for _ in range(D * D):
+                        c, pr = _attempt_uniform(c, pr, L, N, cells)
+        outc.append(c)
+        outp.append(pr / len(shifts))
+    return _merge(np.concatenate(outc), np.concatenate(outp))
+
+
+def dt_distribution(h0, L, N, D, n_sweeps):
+    """Exact state distribution after n sweeps of the double-tiling
+    schedule (4 sets of sub-tiles by their position in the 2 x 2 tile,
+    updated in turn; origin uniform over [0, 2D)^2)."""
+    codes = np.array([encode(h0)], dtype=np.uint64)
+    probs = np.ones(1)
+    for _ in range(n_sweeps):
+        codes, probs = _dt_sweep_codes(codes, probs, L, N, D)
+    return {decode(c, L * L): float(p) for c, p in zip(codes, probs)}
+
+
+def dt_apply_choices(h0, L, N, D, origins, sites):
+    """Double-tiling sweeps along injected choices, in pure Python: per
+    sweep and set k, the sub-tiles with (sx mod 2) + 2 (sy mod 2) = k in
+    increasing sub_id, D*D in-tile indices each."""
+    T = L // D
+    st = tuple(int(v) for v in h0)
+    pos = 0
+    acc = []
+    for (ox, oy) in origins:
+        a = 0
+        for k in range(4):
+            for sid in range(T * T):
+                sx, sy = sid % T, sid // T
+                if (sx % 2) + 2 * (sy % 2) != k:
+                    continue
+                for _ in range(D * D):
+                    r = int(sites[pos]); pos += 1
+                    x = (ox + sx * D + r % D) % L
+                    y = (oy + sy * D + r // D) % L
+                    nxt = deposit(st, L, N, x, y)
+                    a += nxt != st
+                    st = nxt
+        acc.append(a)
+    return st, acc
+
+
 def tc_distribution(h0, L, N, D, n_sweeps):
     """Exact state distribution (float64 probabilities) after n sweeps of
     the tile-checkerboard schedule, as {state tuple: probability}."""

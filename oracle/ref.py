@@ -56,6 +56,12 @@ def lib():
         L.ref_rsos_holds.restype = ctypes.c_int
         L.ref_sums.argtypes = [_i32p, ctypes.c_int, _i64p, _i64p]
         L.ref_power_sums.argtypes = [_i32p, ctypes.c_int, ctypes.c_int64, _i64p]
+        L.ref_run_dt.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_int64, ctypes.c_int64, _i64p]
+        L.ref_run_dt.restype = ctypes.c_int
+        L.ref_run_dt_injected.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int64, _i32p, _i32p, _i64p]
+        L.ref_run_dt_injected.restype = ctypes.c_int
         L.ref_run.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                               ctypes.c_int64, ctypes.c_int64, _i64p]
         L.ref_run.restype = ctypes.c_int
@@ -142,6 +148,24 @@ def run(h, L, N, D, seed, t0, n, log=True):
     lg = np.zeros((max(n, 1), 4), dtype=np.int64) if log else None
     _check(lib().ref_run(_p32(h), L, N, D, seed, t0, n, _p64(lg) if log else None))
     return lg[:n] if log else None
+
+
+def run_dt(h, L, N, D, seed, t0, n, log=True):
+    """Double-tiling sweeps t0..t0+n-1 on h (in place); log as run()."""
+    assert h.dtype == np.int32 and h.flags.c_contiguous and h.size == L * L
+    lg = np.zeros((max(n, 1), 4), dtype=np.int64) if log else None
+    _check(lib().ref_run_dt(_p32(h), L, N, D, seed, t0, n, _p64(lg) if log else None))
+    return lg[:n] if log else None
+
+
+def run_dt_injected(h, L, N, D, origins, sites):
+    """Double-tiling sweeps driven by injected choices (see rsos_ref.h)."""
+    origins = np.ascontiguousarray(origins, dtype=np.int32)
+    sites = np.ascontiguousarray(sites, dtype=np.int32)
+    n = origins.shape[0]
+    lg = np.zeros((max(n, 1), 4), dtype=np.int64)
+    _check(lib().ref_run_dt_injected(_p32(h), L, N, D, n, _p32(origins), _p32(sites), _p64(lg)))
+    return lg[:n]
 
 
 def run_injected(h, L, N, D, origins, sites):

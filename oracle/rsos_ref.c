@@ -307,6 +307,101 @@ int ref_run_injected(int32_t *h, int L, int N, int D, int64_t n,
     return 0;
 }
 
+/* ---------------------------------------------------------------------
+ * Double tiling (Sec. II): tiles of 2D x 2D split into 2 x 2 sub-tiles of
+ * D x D; the sub-tiles fall into 4 sets by their position in the tile,
+ * set k = (sx mod 2) + 2 (sy mod 2) for sub-tile (sx, sy) of the shifted
+ * frame, updated set 0, 1, 2, 3 in turn.  Sub-tiles of one set are separated
+ * by one sub-tile in each direction, so they are independent.  Sub-tile
+ * sub_id = sy*(L/D) + sx of set k takes its D*D sites from Philox counters
+ * (j, sub_id, s, 4 + k) (phase codes 4..7 stay clear of the origin's tag 2).
+ * The origin is drawn as in the checkerboard schedule, mod 2D.
+ * --------------------------------------------------------------------- */
+static int32_t *set_subtiles(int T, int k, int64_t *count)
+{
+    int64_t n = (int64_t)T * T / 4, c = 0;
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int sy = 0; sy < T; ++sy)
+        for (int sx = 0; sx < T; ++sx)
+            if ((sx & 1) + 2 * (sy & 1) == k) ids[c++] = sy * T + sx;
+    *count = c;
+    return ids;
+}
+
+static int64_t sweep_once_dt(int32_t *h, int L, int N, int D, uint64_t seed, uint32_t s,
+                             const int32_t *inj_origin, const int32_t *inj_sites)
+{
+    int T = L / D;
+    int32_t ox, oy;
+    if (inj_origin) { ox = inj_origin[0]; oy = inj_origin[1]; }
+    else ref_origin(D, seed, s, &ox, &oy);
+    int64_t accepted = 0;
+    for (int k = 0; k < 4; ++k) {
+        int64_t n;
+        int32_t *ids = set_subtiles(T, k, &n);
+        int nthreads = g_threads;
+#ifdef _OPENMP
+        if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : accepted) num_threads(nthreads)
+#endif
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t u[1024], v[1024];
+            int sid = ids[i];
+            int sx = sid % T, sy = sid / T;
+            if (inj_sites) {
+                const int32_t *r = inj_sites + ((int64_t)k * n + i) * D * D;
+                for (int a = 0; a < D * D; ++a) { u[a] = r[a] % D; v[a] = r[a] / D; }
+            } else {
+                ref_tile_sites(D, seed, s, (uint32_t)(4 + k), (uint32_t)sid, u, v);
+            }
+            accepted += tile_update(h, L, N, D, ox, oy, sx, sy, u, v);
+        }
+        (void)nthreads;
+        free(ids);
+    }
+    return accepted;
+}
+
+int ref_run_dt(int32_t *h, int L, int N, int D, uint64_t seed, int64_t t0, int64_t n, int64_t *log)
+{
+    if (check_args(L, N, D) != 0 || t0 < 0 || n < 0) return -1;
+    if (t0 + n > (int64_t)UINT32_MAX + 1) return -1;
+    if (!ref_rsos_holds(h, L, N)) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t s = (uint32_t)(t0 + i);
+        int64_t a = sweep_once_dt(h, L, N, D, seed, s, NULL, NULL);
+        if (log) {
+            int64_t s1, s2;
+            ref_sums(h, L, &s1, &s2);
+            log[4 * i + 0] = (int64_t)s + 1;
+            log[4 * i + 1] = s1;
+            log[4 * i + 2] = s2;
+            log[4 * i + 3] = a;
+        }
+    }
+    return 0;
+}
+
+int ref_run_dt_injected(int32_t *h, int L, int N, int D, int64_t n, const int32_t *origins,
+                        const int32_t *sites, int64_t *log)
+{
+    if (check_args(L, N, D) != 0 || n < 0) return -1;
+    if (!ref_rsos_holds(h, L, N)) return -2;
+    int64_t per_sweep = (int64_t)L * L;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t a = sweep_once_dt(h, L, N, D, 0, (uint32_t)i, origins + 2 * i, sites + i * per_sweep);
+        if (log) {
+            int64_t s1, s2;
+            ref_sums(h, L, &s1, &s2);
+            log[4 * i + 0] = i + 1;
+            log[4 * i + 1] = s1;
+            log[4 * i + 2] = s2;
+            log[4 * i + 3] = a;
+        }
+    }
+    return 0;
+}
+
 /* Uniform integer in [0, n) from SplitMix64 by rejection (exactly uniform). */
 static uint32_t uniform_below(uint64_t *st, uint32_t n)
 {

@@ -97,6 +97,14 @@ int64_t ref_rs_injected(int32_t *h, int L, int N, int64_t n_attempts, const int3
 /* Schedule knobs that must not change results: OpenMP threads (0 = serial)
  * and a seed for a random permutation of the tile order inside a phase
  * (0 = increasing tile_id). */
+/* The double-tiling schedule (Sec. II: 2 x 2 sub-tiles per tile, 4 sets
+ * updated in turn; see rsos_ref.c).  Same arguments, log and return codes
+ * as ref_run / ref_run_injected; injected sites list, per sweep and set,
+ * the sub-tiles of that set in increasing sub_id, D*D in-tile indices each. */
+int ref_run_dt(int32_t *h, int L, int N, int D, uint64_t seed, int64_t t0, int64_t n, int64_t *log);
+int ref_run_dt_injected(int32_t *h, int L, int N, int D, int64_t n, const int32_t *origins,
+                        const int32_t *sites, int64_t *log);
+
 void ref_set_threads(int n);
 void ref_set_tile_order_seed(uint64_t seed);
 
