@@ -66,7 +66,8 @@ typedef enum {
  *   D     tile side of the domain decomposition, one of 2, 4, 8, 16
  *         (the paper uses 8 x 8 domains, Sec. II, and tests 16 x 16,
  *         Sec. III.C); part of the result;
- *   flags 0 or RSOS_FLAG_PACKED16 (storage only: results are identical);
+ *   flags 0, RSOS_FLAG_PACKED16 (storage only: results are identical) or
+ *         RSOS_FLAG_DT4 (the double-tiling schedule);
  *   seed  64-bit Philox key. */
 typedef struct {
     int32_t L;
@@ -88,6 +89,16 @@ typedef struct {
  * before a host copy (and that receives h0_host at init).  rsos_time's
  * d_current is NULL in this mode. */
 #define RSOS_FLAG_PACKED16 1
+
+/* The paper's double-tiling schedule (Sec. II) instead of the tile
+ * checkerboard: tiles of 2D x 2D split into 2 x 2 sub-tiles of D x D, the 4
+ * sets of sub-tiles (by position in the tile, set = (sx mod 2) + 2 (sy mod
+ * 2)) updated in turn; sub-tile sub_id of set k draws its sites from Philox
+ * counters (j, sub_id, s, 4 + k); origin as for the checkerboard.  A
+ * different (equally valid) dynamics: results differ from the checkerboard
+ * schedule.  D must be 8 or 16; int32 storage only (not combined with
+ * RSOS_FLAG_PACKED16); single surfaces and batches. */
+#define RSOS_FLAG_DT4 2
 
 /* One record of the per-sweep log: the state after t sweeps.
  *   s1 = sum h, s2 = sum h^2 (exact), accepted = accepted attempts of sweep

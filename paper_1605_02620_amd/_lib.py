@@ -24,6 +24,7 @@ P = ctypes.POINTER
 OK, E_INVAL, E_RSOS, E_OVERFLOW, E_DEVICE, E_NOMEM, E_STATE, E_BUSY = 0, -1, -2, -3, -4, -5, -6, -7
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 FLAG_PACKED16 = 1
+FLAG_DT4 = 2
 
 
 class Params(ctypes.Structure):

@@ -67,6 +67,21 @@ void launch_block16(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *que
     hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, queue);
 }
 
+template <int D, int TX, int TY, int NT, typename E, bool FB>
+void launch_block_dt(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue)
+{
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB, 1>), grid, dim3(NT), 0, st, d, n, queue);
+}
+
+// The double-tiling schedule is built for the domain sizes the paper
+// compares (8 and 16) on int32 storage.
+template <int D, int TX, int TY, int NT, typename E, bool FB>
+constexpr BlockLaunch dt_launcher()
+{
+    if constexpr (D == 8 || D == 16) return launch_block_dt<D, TX, TY, NT, E, FB>;
+    else return nullptr;
+}
+
 struct Variant {
     int D, TX, TY, NT, elem;  // elem: LDS bytes per site (1 and 2: offsets from a block reference)
     BlockLaunch launch;
@@ -76,6 +91,9 @@ struct Variant {
     // shape is not offered for 16-bit storage)
     BlockLaunch launch16;
     BlockLaunch fallback16;
+    // double-tiling schedule (int32 storage; nullptr where not offered)
+    BlockLaunch launch_dt;
+    BlockLaunch fallback_dt;
 };
 
 // int8 staging checks every block's range and queues the few that do not
@@ -83,16 +101,24 @@ struct Variant {
 // staging.
 #define P16(D, TX, TY, NT) \
     launch_block16<D, TX, TY, NT, uint8_t, false>, launch_block16<D, TX, TY, NT, int16_t, true>
+#define DT(D, TX, TY, NT, E, FE) \
+    dt_launcher<D, TX, TY, NT, E, false>(), dt_launcher<D, TX, TY, NT, FE, true>()
+#define DT1(D, TX, TY, NT, E) dt_launcher<D, TX, TY, NT, E, false>(), nullptr
 #define V8(D, TX, TY, NT)                                                                     \
     {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
-     launch_block<D, TX, TY, NT, int16_t, true>, 2, P16(D, TX, TY, NT)}
+     launch_block<D, TX, TY, NT, int16_t, true>, 2, P16(D, TX, TY, NT), DT(D, TX, TY, NT, int8_t, int16_t)}
 #define V8W(D, TX, TY, NT)                                                                    \
     {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
-     launch_block<D, TX, TY, NT, int32_t, true>, 4, nullptr, nullptr}
-#define V16(D, TX, TY, NT) {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, nullptr, nullptr}
+     launch_block<D, TX, TY, NT, int32_t, true>, 4, nullptr, nullptr, DT(D, TX, TY, NT, int8_t, int32_t)}
+#define V16(D, TX, TY, NT) \
+    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, nullptr, nullptr, \
+     DT1(D, TX, TY, NT, int16_t)}
 #define V16P(D, TX, TY, NT) \
-    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, P16(D, TX, TY, NT)}
-#define V32(D, TX, TY, NT) {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, false>, nullptr, 0, nullptr, nullptr}
+    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, P16(D, TX, TY, NT), \
+     DT1(D, TX, TY, NT, int16_t)}
+#define V32(D, TX, TY, NT) \
+    {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, false>, nullptr, 0, nullptr, nullptr, \
+     DT1(D, TX, TY, NT, int32_t)}
 // In order of preference; the first one that fits every surface is used.
 const Variant kVariants[] = {
     V16P(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
@@ -102,14 +128,17 @@ const Variant kVariants[] = {
     V16P(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
 };
 #undef P16
+#undef DT
+#undef DT1
 #undef V8
 #undef V8W
 #undef V16
 #undef V16P
 #undef V32
 
-bool variant_fits(const Variant &v, int L, int N, bool packed)
+bool variant_fits(const Variant &v, int L, int N, bool packed, bool dt = false)
 {
+    if (dt && (packed || !v.launch_dt)) return false;
     const int T = L / v.D;
     const int rw = v.TX * v.D + 2 * (v.D + 1), rh = v.TY * v.D + 2 * (v.D + 1);
     const int rwl = packed ? (rw + 14) & ~7 : (rw + 6) & ~3;
@@ -128,7 +157,8 @@ bool variant_fits(const Variant &v, int L, int N, bool packed)
 // First fitting variant for D that fits every (L, N) (optionally forced by
 // the RSOS_VARIANT environment variable "TXxTYxNTxELEM", e.g. "16x8x128x2";
 // ELEM is 16 for the 16-bit storage kernels).
-const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN, bool packed = false)
+const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN, bool packed = false,
+                            bool dt = false)
 {
     const char *force = getenv("RSOS_VARIANT");
     for (const Variant &v : kVariants) {
@@ -139,7 +169,7 @@ const Variant *pick_variant(int D, const std::vector<std::pair<int, int>> &LN, b
             if (strcmp(force, want) != 0) continue;
         }
         bool ok = true;
-        for (auto &ln : LN) ok = ok && variant_fits(v, ln.first, ln.second, packed);
+        for (auto &ln : LN) ok = ok && variant_fits(v, ln.first, ln.second, packed, dt);
         if (ok) return &v;
     }
     return nullptr;
@@ -162,18 +192,25 @@ rsos_status check_packed(const rsos_params *p)
 }
 
 typedef void (*LdsLaunch)(dim3, size_t, hipStream_t, SurfDev *, const int *);
-template <int D>
+template <int D, int SCHED>
 void launch_lds(dim3 grid, size_t shm, hipStream_t st, SurfDev *d, const int *w)
 {
-    hipLaunchKernelGGL((rsosk::lds_run<D, 256>), grid, dim3(256), shm, st, d, w);
+    hipLaunchKernelGGL((rsosk::lds_run<D, 256, SCHED>), grid, dim3(256), shm, st, d, w);
 }
-LdsLaunch lds_launcher(int D)
+LdsLaunch lds_launcher(int D, int sched = 0)
 {
+    if (sched == 1) {
+        switch (D) {
+        case 8: return launch_lds<8, 1>;
+        case 16: return launch_lds<16, 1>;
+        }
+        return nullptr;
+    }
     switch (D) {
-    case 2: return launch_lds<2>;
-    case 4: return launch_lds<4>;
-    case 8: return launch_lds<8>;
-    case 16: return launch_lds<16>;
+    case 2: return launch_lds<2, 0>;
+    case 4: return launch_lds<4, 0>;
+    case 8: return launch_lds<8, 0>;
+    case 16: return launch_lds<16, 0>;
     }
     return nullptr;
 }
@@ -187,7 +224,15 @@ rsos_status check_params(const rsos_params *p)
     if (p->L < 2 * p->D || p->L > 65536 || p->L % (2 * p->D) != 0)
         return fail(RSOS_E_INVAL, "L=%d: must be a multiple of 2D=%d in [2D, 65536]", p->L, 2 * p->D);
     if (p->N < 1) return fail(RSOS_E_INVAL, "N=%d: must be >= 1", p->N);
-    if (p->flags & ~RSOS_FLAG_PACKED16) return fail(RSOS_E_INVAL, "unknown flags 0x%x", (unsigned)p->flags);
+    if (p->flags & ~(RSOS_FLAG_PACKED16 | RSOS_FLAG_DT4))
+        return fail(RSOS_E_INVAL, "unknown flags 0x%x", (unsigned)p->flags);
+    if (p->flags & RSOS_FLAG_DT4) {
+        if (p->flags & RSOS_FLAG_PACKED16)
+            return fail(RSOS_E_INVAL, "the double-tiling schedule runs on int32 storage");
+        if (p->D != 8 && p->D != 16) return fail(RSOS_E_INVAL, "double tiling: D must be 8 or 16");
+        if (!uses_lds(p->L) && !pick_variant(p->D, {{p->L, p->N}}, false, true))
+            return fail(RSOS_E_INVAL, "double tiling: no tile-block shape fits L=%d, N=%d", p->L, p->N);
+    }
     if (p->flags & RSOS_FLAG_PACKED16) return check_packed(p);
     return RSOS_OK;
 }
@@ -285,6 +330,7 @@ struct Staging {
 struct SurfaceGroup {
     int D = 8;
     bool packed = false;               // heights kept as 16-bit residues
+    int sched = 0;                     // 0: tile checkerboard, 1: double tiling
     hipStream_t stream = nullptr;
     bool failed = false;
     std::vector<SurfDev> host;         // host mirror (t, t_end kept current)
@@ -328,7 +374,7 @@ struct SurfaceGroup {
                     return fail(RSOS_E_INVAL, "height buffers must be 16-byte aligned");
         }
         if (!blk_idx.empty()) {
-            variant = pick_variant(D, LN, packed);
+            variant = pick_variant(D, LN, packed, sched == 1);
             if (!variant) return fail(RSOS_E_INVAL, "no tile-block shape fits these lattice sizes");
         }
         if (packed && !lds_idx.empty()) return fail(RSOS_E_INVAL, "16-bit storage needs the tile-block path");
@@ -408,7 +454,7 @@ struct SurfaceGroup {
     {
         if (n <= 0) return RSOS_OK;
         if (!lds_idx.empty()) {
-            lds_launcher(D)(dim3((unsigned)lds_idx.size()), lds_bytes, stream, d_desc, d_lds_idx);
+            lds_launcher(D, sched)(dim3((unsigned)lds_idx.size()), lds_bytes, stream, d_desc, d_lds_idx);
             HIP_TRY(hipGetLastError());
         }
         if (blk_idx.empty()) return RSOS_OK;
@@ -435,8 +481,8 @@ struct SurfaceGroup {
     void launch_block_sweep()
     {
         const int n = (int)blk_idx.size();
-        BlockLaunch main = packed ? variant->launch16 : variant->launch;
-        BlockLaunch fb = packed ? variant->fallback16 : variant->fallback;
+        BlockLaunch main = packed ? variant->launch16 : sched == 1 ? variant->launch_dt : variant->launch;
+        BlockLaunch fb = packed ? variant->fallback16 : sched == 1 ? variant->fallback_dt : variant->fallback;
         main(dim3(total_blocks), stream, d_desc, n, d_queue);
         if (fb) fb(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n, d_queue);
     }
@@ -717,6 +763,7 @@ rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, in
     SurfaceGroup &g = s->g;
     g.D = p->D;
     g.packed = (p->flags & RSOS_FLAG_PACKED16) != 0;
+    g.sched = (p->flags & RSOS_FLAG_DT4) ? 1 : 0;
     g.stream = (hipStream_t)stream;
     const size_t n = (size_t)p->L * p->L;
     SurfDev d = {};
@@ -825,6 +872,10 @@ rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len)
     if (g.variant && g.packed)
         snprintf(buf, (size_t)len, "block_sweep16<%d,%d,%d,%d,uint8>", g.variant->D, g.variant->TX,
                  g.variant->TY, g.variant->NT);
+    else if (g.variant && g.sched == 1)
+        snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s,dt>", g.variant->D, g.variant->TX,
+                 g.variant->TY, g.variant->NT,
+                 g.variant->elem == 1 ? "int8" : g.variant->elem == 2 ? "int16" : "int32");
     else if (g.variant)
         snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s>", g.variant->D, g.variant->TX,
                  g.variant->TY, g.variant->NT,
@@ -875,6 +926,7 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
     SurfaceGroup &g = b->g;
     g.D = p[0].D;
     g.packed = (p[0].flags & RSOS_FLAG_PACKED16) != 0;
+    g.sched = (p[0].flags & RSOS_FLAG_DT4) ? 1 : 0;
     g.stream = (hipStream_t)stream;
     long long pool_elems = 0;
     for (int i = 0; i < n; ++i) pool_elems = std::max(pool_elems, offsets[i] + (long long)p[i].L * p[i].L);

@@ -356,6 +356,70 @@ __device__ __forceinline__ void block_phases(E *lds, int off, int bx, int by, in
     __syncthreads();
 }
 
+// The double-tiling schedule on the same block (TX x TY sub-tiles of D,
+// TX and TY even, so a block holds whole 2 x 2 tiles).  Set k = (sx mod 2)
+// + 2 (sy mod 2) is updated in phase k with Philox phase code 4 + k.  The
+// block's border sub-tiles read sub-tiles of the neighbouring blocks; those
+// updated in an earlier phase are recomputed here, in their phase: the
+// set-0 sub-tiles of the frame column right of the block and of the frame
+// row below it (and the corner between them) in phase 0, the set-1
+// sub-tiles of the row below in phase 1, the set-2 sub-tiles of the column
+// to the right in phase 2.  Their inputs are original values or values
+// this block has already brought to the same phase; the frames above and
+// to the left are read only before their own updates.  Counts of frame
+// sub-tiles are dropped.
+template <int D, int TX, int TY, int NT, int RWL, typename E, typename Q>
+__device__ __forceinline__ void block_phases_dt(E *lds, int off, int bx, int by, int T, uint32_t s, int N,
+                                                uint32_t k0, uint32_t k1, int &acc, Q &q)
+{
+    static_assert(TX % 2 == 0 && TY % 2 == 0, "blocks hold whole 2 x 2 tiles");
+    constexpr int RING = D + 1, Q4 = TX * TY / 4;
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        const int extra = k == 0 ? TX / 2 + TY / 2 + 1 : k == 1 ? TX / 2 : k == 2 ? TY / 2 : 0;
+        for (int i = threadIdx.x; i < Q4 + extra; i += NT) {
+            int ltx, lty;
+            if (i < Q4) {
+                lty = 2 * (i / (TX / 2)) + (k >> 1);
+                ltx = 2 * (i % (TX / 2)) + (k & 1);
+            } else {
+                const int g = i - Q4;
+                if (k == 0) {
+                    if (g < TY / 2) { ltx = TX; lty = 2 * g; }
+                    else if (g < TY / 2 + TX / 2) { lty = TY; ltx = 2 * (g - TY / 2); }
+                    else { ltx = TX; lty = TY; }
+                } else if (k == 1) {
+                    lty = TY;
+                    ltx = 2 * g + 1;
+                } else {
+                    ltx = TX;
+                    lty = 2 * g + 1;
+                }
+            }
+            int gsx = bx * TX + ltx, gsy = by * TY + lty;
+            if (gsx >= T) gsx -= T;
+            if (gsy >= T) gsy -= T;
+            const int base = (lty * D + RING) * RWL + ltx * D + off;
+            int a = 0;
+            Q qq = 0;
+            tile_attempts<D, RWL, E, Q>(lds, base, (uint32_t)(gsy * T + gsx), s, 4u + (uint32_t)k, N, k0, k1, a, qq);
+            if (i < Q4) { acc += a; q += qq; }
+        }
+        __syncthreads();
+    }
+}
+
+// Schedule selector: 0 = tile checkerboard, 1 = double tiling.
+template <int SCHED, int D, int TX, int TY, int NT, int RWL, typename E, typename Q>
+__device__ __forceinline__ void sweep_phases(E *lds, int off, int bx, int by, int T, uint32_t s, int N,
+                                             uint32_t k0, uint32_t k1, int &acc, Q &q)
+{
+    if constexpr (SCHED == 0)
+        block_phases<D, TX, TY, NT, RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    else
+        block_phases_dt<D, TX, TY, NT, RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+}
+
 // Adds the block's increments (A, 2 sum(base + c) + A, A) of S1, S2 and
 // the accepted count to one of the surface's accumulator slots (q = sum of
 // the staged values c before the accepted deposits; base is the height that
@@ -401,7 +465,7 @@ struct StageLimits {
 // the table); an int8 workgroup whose block does not fit queues it and
 // stops.  FALLBACK = true: workgroups walk the queue of the preceding
 // int8 launch.
-template <int D, int TX, int TY, int NT, typename E, bool FALLBACK>
+template <int D, int TX, int TY, int NT, typename E, bool FALLBACK, int SCHED = 0>
 __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf,
                                                   int *__restrict__ queue)
 {
@@ -504,7 +568,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     const int off = G::RING + cpad;  // LDS column of block column 0
     int acc = 0;
     Q q = 0;
-    block_phases<D, TX, TY, NT, G::RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    sweep_phases<SCHED, D, TX, TY, NT, G::RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
 
     // ---- store the block: aligned 16-byte chunks (LDS and global columns
     // share their alignment), masked single stores in the partial chunks
@@ -651,7 +715,7 @@ template <> struct Stage16<int16_t> {
 // Host requirements as for block_sweep, with chunks of 8 cells: L % 8 == 0,
 // RWL <= L, N L <= 32766, N D <= 96, and N (RW + RH + 4) + D^2 <= 32767 for
 // the int16 fallback.
-template <int D, int TX, int TY, int NT, typename E, bool FALLBACK>
+template <int D, int TX, int TY, int NT, typename E, bool FALLBACK, int SCHED = 0>
 __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ descs, int nsurf,
                                                     int *__restrict__ queue)
 {
@@ -754,7 +818,7 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
     const int off = G::RING + cpad;
     int acc = 0;
     int q = 0;
-    block_phases<D, TX, TY, NT, G::RWL, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    sweep_phases<SCHED, D, TX, TY, NT, G::RWL, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
 
     // ---- store: 16-byte chunks of 8 residues; 16-bit stores in the partial
     // chunks at both ends of each row
@@ -898,7 +962,7 @@ __device__ __forceinline__ int tile_attempts_torus(int32_t *h, int L, int x0, in
     return acc;
 }
 
-template <int D, int NT>
+template <int D, int NT, int SCHED = 0>
 __global__ __launch_bounds__(NT) void lds_run(SurfDev *__restrict__ descs, const int *__restrict__ which)
 {
     extern __shared__ int32_t lat[];
@@ -921,14 +985,27 @@ __global__ __launch_bounds__(NT) void lds_run(SurfDev *__restrict__ descs, const
         const int ox = (int)(org.v[0] % (2u * D));
         const int oy = (int)(org.v[1] % (2u * D));
         long long acc = 0;
-        for (int p = 0; p < 2; ++p) {
-            for (int k = threadIdx.x; k < half; k += NT) {
-                const int ty = k / (T / 2);
-                const int tx = 2 * (k % (T / 2)) + ((ty + p) & 1);
-                acc += tile_attempts_torus<D>(lat, L, ox + tx * D, oy + ty * D,
-                                              (uint32_t)(ty * T + tx), s, (uint32_t)p, N, k0, k1);
+        if constexpr (SCHED == 0) {
+            for (int p = 0; p < 2; ++p) {
+                for (int k = threadIdx.x; k < half; k += NT) {
+                    const int ty = k / (T / 2);
+                    const int tx = 2 * (k % (T / 2)) + ((ty + p) & 1);
+                    acc += tile_attempts_torus<D>(lat, L, ox + tx * D, oy + ty * D,
+                                                  (uint32_t)(ty * T + tx), s, (uint32_t)p, N, k0, k1);
+                }
+                __syncthreads();
             }
-            __syncthreads();
+        } else {
+            // double tiling: set p = (sx mod 2) + 2 (sy mod 2), phase code 4 + p
+            for (int p = 0; p < 4; ++p) {
+                for (int k = threadIdx.x; k < half / 2; k += NT) {
+                    const int sy = 2 * (k / (T / 2)) + (p >> 1);
+                    const int sx = 2 * (k % (T / 2)) + (p & 1);
+                    acc += tile_attempts_torus<D>(lat, L, ox + sx * D, oy + sy * D,
+                                                  (uint32_t)(sy * T + sx), s, 4u + (uint32_t)p, N, k0, k1);
+                }
+                __syncthreads();
+            }
         }
         long long s1 = 0, s2 = 0;
         for (int i = threadIdx.x; i < n; i += NT) {

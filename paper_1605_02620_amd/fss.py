@@ -38,12 +38,13 @@ def _window_w(lg, t_from):
     return float(np.sqrt(lg["w2"][sel]).mean())
 
 
-def calibrate(N, D=8, sizes=(32, 64), realizations=16, growth=(8, 64), seed0=10_000):
+def calibrate(N, D=8, sizes=(32, 64), realizations=16, growth=(8, 64), seed0=10_000,
+              schedule="checkerboard"):
     """a_N, b_N, alpha and beta of Eq. (7) from a pilot batch of small
     systems run far into saturation (t = 40 L_max^1.62)."""
     t_run = int(40 * max(sizes) ** 1.62)
     specs = [(L, N, seed0 + k) for L in sizes for k in range(realizations)]
-    b = Batch(specs, D=D, log_cap=t_run + 1)
+    b = Batch(specs, D=D, log_cap=t_run + 1, schedule=schedule)
     b.sweep(t_run)
     logs = [b.log(i, 1, t_run) for i in range(len(specs))]
     b.close()
@@ -62,14 +63,14 @@ def calibrate(N, D=8, sizes=(32, 64), realizations=16, growth=(8, 64), seed0=10_
 
 
 def run(sizes=(32, 64, 128, 256, 512), N=1, realizations=32, D=8, start=2.0, window=2.0,
-        moment_samples=32, calib=None, seed0=0, min_window=256):
+        moment_samples=32, calib=None, seed0=0, min_window=256, schedule="checkerboard"):
     """The steady-state workload.  Every size gets `realizations` surfaces
     (seeds seed0, seed0+1, ...); surface of size L runs to
     t_end = t_start + max(window t*, min_window) with t_start = start t*(L).
     Returns per-size W_sat (time and ensemble mean of W over t >= t_start,
     with its standard error over realizations), the W^2 and height shape
     statistics in the window, alpha_fit, and alpha_eff at the midpoints."""
-    calib = calib or calibrate(N, D)
+    calib = calib or calibrate(N, D, schedule=schedule)
     sizes = sorted(int(L) for L in sizes)
     ts = {L: t_steady(L, **calib) for L in sizes}
     t_start = {L: int(math.ceil(start * ts[L])) for L in sizes}
@@ -77,7 +78,7 @@ def run(sizes=(32, 64, 128, 256, 512), N=1, realizations=32, D=8, start=2.0, win
     specs = [(L, N, seed0 + k) for L in sizes for k in range(realizations)]
     ends = np.array([t_end[L] for (L, _, _) in specs], dtype=np.int64)
     log_cap = int(max(t_end[L] - t_start[L] for L in sizes)) + 2
-    b = Batch(specs, D=D, log_cap=log_cap)
+    b = Batch(specs, D=D, log_cap=log_cap, schedule=schedule)
     # moment samples: evenly spaced in each size's window
     sample_t = {L: np.unique(np.linspace(t_start[L], t_end[L], moment_samples).astype(np.int64))
                 for L in sizes}
@@ -123,7 +124,7 @@ def run(sizes=(32, 64, 128, 256, 512), N=1, realizations=32, D=8, start=2.0, win
     wsat = [per_size[L]["W_sat"] for L in sizes]
     alpha_fit, _ = analysis.power_fit(sizes, wsat)
     mid, a_eff = analysis.effective_exponent(sizes, wsat)
-    return {"N": N, "D": D, "realizations": realizations, "calibration": calib,
+    return {"N": N, "D": D, "schedule": schedule, "realizations": realizations, "calibration": calib,
             "sizes": per_size, "alpha_fit": alpha_fit,
             "alpha_eff": [(float(x), float(y)) for x, y in zip(mid, a_eff)],
             "attempts": attempts, "wall_s": wall, "attempts_per_ns": attempts / (wall * 1e9),

@@ -29,8 +29,13 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _params(L, N, D, seed, packed=False):
-    flags = _lib.FLAG_PACKED16 if packed else 0
+SCHEDULES = {"checkerboard": 0, "double": _lib.FLAG_DT4}
+
+
+def _params(L, N, D, seed, packed=False, schedule="checkerboard"):
+    if schedule not in SCHEDULES:
+        raise ValueError(f"schedule must be one of {sorted(SCHEDULES)}")
+    flags = (_lib.FLAG_PACKED16 if packed else 0) | SCHEDULES[schedule]
     return Params(int(L), int(N), int(D), flags, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)).value)
 
 
@@ -45,10 +50,14 @@ class Surface:
     packed=True keeps the heights as 16-bit residues in device memory
     (RSOS_FLAG_PACKED16; N*L <= 32766): identical results, half the bytes
     per sweep.  The two int32[L*L] tensors are then the residue pair and
-    the int32 readout scratch."""
+    the int32 readout scratch.
+
+    schedule="double" runs the paper's double-tiling schedule (RSOS_FLAG_DT4)
+    instead of the tile checkerboard."""
 
     def __init__(self, L: int, N: int = 1, seed: int = 0, D: int = 8, h0=None, t0: int = 0,
-                 log_cap: int = 0, device="cuda", stream=None, packed: bool = False):
+                 log_cap: int = 0, device="cuda", stream=None, packed: bool = False,
+                 schedule: str = "checkerboard"):
         dev = _require_gpu(device)
         self.L, self.N, self.D, self.seed = int(L), int(N), int(D), int(seed)
         self.packed = bool(packed)
@@ -57,7 +66,8 @@ class Surface:
         n = self.L * self.L
         self.bufs = (torch.empty(n, dtype=torch.int32, device=dev),
                      torch.empty(n, dtype=torch.int32, device=dev))
-        p = _params(L, N, D, seed, self.packed)
+        self.schedule = schedule
+        p = _params(L, N, D, seed, self.packed, schedule)
         h0p = None
         if h0 is not None:
             self._h0 = np.ascontiguousarray(np.asarray(h0, dtype=np.int32).reshape(-1))
@@ -145,7 +155,7 @@ class Batch:
     ALIGN = 64  # elements (256 bytes) between surfaces in the pool
 
     def __init__(self, specs, D: int = 8, log_cap: int = 0, device="cuda", stream=None,
-                 packed: bool = False):
+                 packed: bool = False, schedule: str = "checkerboard"):
         dev = _require_gpu(device)
         self.specs = [(int(L), int(N), int(seed)) for (L, N, seed) in specs]
         self.D = int(D)
@@ -158,7 +168,9 @@ class Batch:
         self.offsets = np.asarray(offs, dtype=np.int64)
         self.pool = torch.empty(max(off, 1), dtype=torch.int32, device=dev)
         self.work = torch.empty(max(off, 1), dtype=torch.int32, device=dev)
-        ps = (Params * len(self.specs))(*[_params(L, N, D, s, self.packed) for (L, N, s) in self.specs])
+        self.schedule = schedule
+        ps = (Params * len(self.specs))(*[_params(L, N, D, s, self.packed, schedule)
+                                          for (L, N, s) in self.specs])
         self._h = ctypes.c_void_p()
         check(lib().rsos_batch_init(ctypes.byref(self._h), len(self.specs), ps,
                                     ctypes.c_void_p(self.pool.data_ptr()),

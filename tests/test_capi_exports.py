@@ -92,8 +92,8 @@ def test_status_strings(so):
 
 def test_parameter_checks_without_gpu(so):
     """rsos_init validates its parameters on the host before any device call:
-    unknown flags, and the limits of the 16-bit storage mode (N*L <= 32766,
-    the tile-block path, N*D <= 96)."""
+    unknown flags, the limits of the 16-bit storage mode (N*L <= 32766, the
+    tile-block path, N*D <= 96) and of the double-tiling schedule."""
     from paper_1605_02620_amd import _lib
     lib = _lib.lib()
 
@@ -103,8 +103,15 @@ def test_parameter_checks_without_gpu(so):
         st = lib.rsos_init(ctypes.byref(h), ctypes.byref(p), None, None, None, 0, 0, None)
         return st, lib.rsos_last_error().decode()
 
-    assert init(1024, 1, 8, 2)[0] == _lib.E_INVAL
-    assert "flags" in init(1024, 1, 8, 2)[1]
+    assert init(1024, 1, 8, 4)[0] == _lib.E_INVAL
+    assert "flags" in init(1024, 1, 8, 4)[1]
+    st, msg = init(1024, 1, 4, _lib.FLAG_DT4)                # double tiling: D = 8 or 16
+    assert st == _lib.E_INVAL and "double tiling" in msg
+    st, msg = init(1024, 1, 8, _lib.FLAG_DT4 | _lib.FLAG_PACKED16)
+    assert st == _lib.E_INVAL and "double-tiling" in msg
+    for (L, N, D) in [(1024, 1, 8), (64, 1, 8), (512, 3, 16)]:
+        st, msg = init(L, N, D, _lib.FLAG_DT4)
+        assert st == _lib.E_INVAL and "d_h" in msg, (L, N, D, msg)
     st, msg = init(16384, 2, 8, _lib.FLAG_PACKED16)          # N L = 32768
     assert st == _lib.E_INVAL and "32766" in msg
     st, msg = init(64, 1, 8, _lib.FLAG_PACKED16)             # LDS-path size
