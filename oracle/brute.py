@@ -169,6 +169,68 @@ def dt_apply_choices(h0, L, N, D, origins, sites):
     return st, acc
 
 
+def _ms_sweep_codes(codes, probs, L, N, D):
+    """One lock-step sweep of a single realization: per tile, 2 D^2
+    selections, each applied with probability 1/2 at a uniform in-tile site."""
+    T = L // D
+    shifts = [(ox, oy) for oy in range(2 * D) for ox in range(2 * D)]
+    outc, outp = [], []
+    for (ox, oy) in shifts:
+        c, pr = codes, probs
+        for p in (0, 1):
+            for ty in range(T):
+                for tx in range(T):
+                    if (tx + ty) % 2 != p:
+                        continue
+                    cells = [((ox + tx * D + u) % L, (oy + ty * D + v) % L)
+                             for v in range(D) for u in range(D)]
+                    for _ in range(2 * D * D):
+                        c2, p2 = _attempt_uniform(c, pr, L, N, cells)
+                        c, pr = _merge(np.concatenate([c, c2]), np.concatenate([pr * 0.5, p2 * 0.5]))
+        outc.append(c)
+        outp.append(pr / len(shifts))
+    return _merge(np.concatenate(outc), np.concatenate(outp))
+
+
+def ms_distribution(h0, L, N, D, n_sweeps):
+    """Exact state distribution of one realization of the lock-step
+    schedule after n sweeps (its coins make each selection a fair mixture
+    of doing nothing and a uniform in-tile attempt)."""
+    codes = np.array([encode(h0)], dtype=np.uint64)
+    probs = np.ones(1)
+    for _ in range(n_sweeps):
+        codes, probs = _ms_sweep_codes(codes, probs, L, N, D)
+    return {decode(c, L * L): float(p) for c, p in zip(codes, probs)}
+
+
+def ms_apply_choices(h0, L, N, D, origins, sites, coins):
+    """One lock-step realization along injected choices, pure Python: per
+    sweep and colour, tiles in increasing tile_id, 2 D^2 (site, coin)
+    pairs each."""
+    T = L // D
+    st = tuple(int(v) for v in h0)
+    pos = 0
+    acc = []
+    for (ox, oy) in origins:
+        a = 0
+        for p in (0, 1):
+            for tid in range(T * T):
+                tx, ty = tid % T, tid // T
+                if (tx + ty) % 2 != p:
+                    continue
+                for _ in range(2 * D * D):
+                    r, coin = int(sites[pos]), int(coins[pos]); pos += 1
+                    if not coin:
+                        continue
+                    x = (ox + tx * D + r % D) % L
+                    y = (oy + ty * D + r // D) % L
+                    nxt = deposit(st, L, N, x, y)
+                    a += nxt != st
+                    st = nxt
+        acc.append(a)
+    return st, acc
+
+
 def tc_distribution(h0, L, N, D, n_sweeps):
     """Exact state distribution (float64 probabilities) after n sweeps of
     the tile-checkerboard schedule, as {state tuple: probability}."""

@@ -56,6 +56,12 @@ def lib():
         L.ref_rsos_holds.restype = ctypes.c_int
         L.ref_sums.argtypes = [_i32p, ctypes.c_int, _i64p, _i64p]
         L.ref_power_sums.argtypes = [_i32p, ctypes.c_int, ctypes.c_int64, _i64p]
+        L.ref_run_ms.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _i64p]
+        L.ref_run_ms.restype = ctypes.c_int
+        L.ref_run_ms_injected.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int64, _i32p, _i32p, _i32p, _i64p]
+        L.ref_run_ms_injected.restype = ctypes.c_int
         L.ref_run_dt.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                  ctypes.c_int64, ctypes.c_int64, _i64p]
         L.ref_run_dt.restype = ctypes.c_int
@@ -156,6 +162,28 @@ def run_dt(h, L, N, D, seed, t0, n, log=True):
     lg = np.zeros((max(n, 1), 4), dtype=np.int64) if log else None
     _check(lib().ref_run_dt(_p32(h), L, N, D, seed, t0, n, _p64(lg) if log else None))
     return lg[:n] if log else None
+
+
+def run_ms(h, L, N, D, seed, t0, n, log=True):
+    """Multisurface lock-step sweeps of R realizations; h is int32[R, L*L]
+    (modified in place).  Returns int64[R, n, 4] = (t, S1, S2, A) or None."""
+    assert h.dtype == np.int32 and h.flags.c_contiguous and h.ndim == 2 and h.shape[1] == L * L
+    R = h.shape[0]
+    lg = np.zeros((R, max(n, 1), 4), dtype=np.int64) if log else None
+    _check(lib().ref_run_ms(_p32(h), R, L, N, D, seed, t0, n, _p64(lg) if log else None))
+    return lg[:, :n] if log else None
+
+
+def run_ms_injected(h, L, N, D, origins, sites, coins):
+    """One realization of the lock-step schedule along injected choices."""
+    origins = np.ascontiguousarray(origins, dtype=np.int32)
+    sites = np.ascontiguousarray(sites, dtype=np.int32)
+    coins = np.ascontiguousarray(coins, dtype=np.int32)
+    n = origins.shape[0]
+    lg = np.zeros((max(n, 1), 4), dtype=np.int64)
+    _check(lib().ref_run_ms_injected(_p32(h), L, N, D, n, _p32(origins), _p32(sites), _p32(coins),
+                                     _p64(lg)))
+    return lg[:n]
 
 
 def run_dt_injected(h, L, N, D, origins, sites):

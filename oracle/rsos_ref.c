@@ -402,6 +402,143 @@ int ref_run_dt_injected(int32_t *h, int L, int N, int D, int64_t n, const int32_
     return 0;
 }
 
+/* ---------------------------------------------------------------------
+ * Multisurface lock-step (Sec. II): R realizations share one sequence of
+ * selected sites, and each realization applies each selection only with
+ * probability 1/2 (its own coin), which breaks the correlation between
+ * them.  A sweep makes 2 D^2 selections per tile and phase, so every
+ * realization receives L^2 attempts per sweep on average.  Selection a of
+ * tile tile_id in phase p of sweep s takes its site field from Philox
+ * (j, tile_id, s, p) with the checkerboard layout, a in [0, 2 D^2);
+ * realization r's coin is bit (a mod 32) of word (a div 32) mod 4 of Philox
+ * (a div 128, tile_id, s, 8 + 2r + p).  Origin and colours as for the
+ * checkerboard.
+ * --------------------------------------------------------------------- */
+static void tile_fields(int D, uint64_t seed, uint32_t s, uint32_t p, uint32_t tile_id, int count,
+                        int32_t *u, int32_t *v)
+{
+    uint32_t key[2];
+    seed_to_key(seed, key);
+    int b = 2 * log2_exact(D);
+    int f = 32 / b;
+    int per_call = 4 * f;
+    uint32_t r[4] = {0, 0, 0, 0};
+    int32_t fields[16];
+    for (int a = 0; a < count; ++a) {
+        if (a % per_call == 0) {
+            uint32_t ctr[4] = {(uint32_t)(a / per_call), tile_id, s, p};
+            ref_philox4x32_10(ctr, key, r);
+        }
+        int w = (a % per_call) / f;
+        int k = a % f;
+        if (k == 0) ref_word_fields(D, r[w], fields);
+        u[a] = fields[k] % D;
+        v[a] = fields[k] / D;
+    }
+}
+
+static int ms_coin(uint64_t seed, uint32_t s, uint32_t p, uint32_t tile_id, int r, int a)
+{
+    uint32_t key[2], out[4];
+    seed_to_key(seed, key);
+    uint32_t ctr[4] = {(uint32_t)(a / 128), tile_id, s, 8u + 2u * (uint32_t)r + p};
+    ref_philox4x32_10(ctr, key, out);
+    return (int)((out[(a / 32) % 4] >> (a % 32)) & 1u);
+}
+
+/* One sweep of one realization; choices from the seed, or injected
+ * (inj_sites: per phase, tiles of that colour in increasing tile_id, 2 D^2
+ * in-tile indices each; inj_coins: the same positions, 0 or 1). */
+static int64_t sweep_once_ms(int32_t *h, int L, int N, int D, uint64_t seed, uint32_t s, int r,
+                             const int32_t *inj_origin, const int32_t *inj_sites,
+                             const int32_t *inj_coins)
+{
+    int T = L / D;
+    int32_t ox, oy;
+    if (inj_origin) { ox = inj_origin[0]; oy = inj_origin[1]; }
+    else ref_origin(D, seed, s, &ox, &oy);
+    int64_t accepted = 0;
+    const int sel = 2 * D * D;
+    for (int p = 0; p < 2; ++p) {
+        int64_t n;
+        int32_t *ids = phase_tiles(T, p, 0, s, &n);
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t u[2048], v[2048];
+            int tid = ids[i];
+            int tx = tid % T, ty = tid / T;
+            if (inj_sites) {
+                const int32_t *q = inj_sites + ((int64_t)p * n + i) * sel;
+                for (int a = 0; a < sel; ++a) { u[a] = q[a] % D; v[a] = q[a] / D; }
+            } else {
+                tile_fields(D, seed, s, (uint32_t)p, (uint32_t)tid, sel, u, v);
+            }
+            for (int a = 0; a < sel; ++a) {
+                int coin = inj_coins ? inj_coins[((int64_t)p * n + i) * sel + a]
+                                     : ms_coin(seed, s, (uint32_t)p, (uint32_t)tid, r, a);
+                if (!coin) continue;
+                int x = wrap((int64_t)ox + (int64_t)tx * D + u[a], L);
+                int y = wrap((int64_t)oy + (int64_t)ty * D + v[a], L);
+                accepted += ref_attempt(h, L, N, x, y);
+            }
+        }
+        free(ids);
+    }
+    return accepted;
+}
+
+int ref_run_ms(int32_t *h, int R, int L, int N, int D, uint64_t seed, int64_t t0, int64_t n,
+               int64_t *log)
+{
+    if (check_args(L, N, D) != 0 || R < 1 || t0 < 0 || n < 0) return -1;
+    if (t0 + n > (int64_t)UINT32_MAX + 1) return -1;
+    for (int r = 0; r < R; ++r)
+        if (!ref_rsos_holds(h + (int64_t)r * L * L, L, N)) return -2;
+    int nthreads = g_threads;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int r = 0; r < R; ++r) {
+        int32_t *hr = h + (int64_t)r * L * L;
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t s = (uint32_t)(t0 + i);
+            int64_t a = sweep_once_ms(hr, L, N, D, seed, s, r, NULL, NULL, NULL);
+            if (log) {
+                int64_t s1, s2;
+                ref_sums(hr, L, &s1, &s2);
+                int64_t *e = log + 4 * ((int64_t)r * n + i);
+                e[0] = (int64_t)s + 1;
+                e[1] = s1;
+                e[2] = s2;
+                e[3] = a;
+            }
+        }
+    }
+    (void)nthreads;
+    return 0;
+}
+
+int ref_run_ms_injected(int32_t *h, int L, int N, int D, int64_t n, const int32_t *origins,
+                        const int32_t *sites, const int32_t *coins, int64_t *log)
+{
+    if (check_args(L, N, D) != 0 || n < 0) return -1;
+    if (!ref_rsos_holds(h, L, N)) return -2;
+    int64_t per_sweep = 2 * (int64_t)L * L;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t a = sweep_once_ms(h, L, N, D, 0, (uint32_t)i, 0, origins + 2 * i, sites + i * per_sweep,
+                                  coins + i * per_sweep);
+        if (log) {
+            int64_t s1, s2;
+            ref_sums(h, L, &s1, &s2);
+            log[4 * i + 0] = i + 1;
+            log[4 * i + 1] = s1;
+            log[4 * i + 2] = s2;
+            log[4 * i + 3] = a;
+        }
+    }
+    return 0;
+}
+
 /* Uniform integer in [0, n) from SplitMix64 by rejection (exactly uniform). */
 static uint32_t uniform_below(uint64_t *st, uint32_t n)
 {

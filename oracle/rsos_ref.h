@@ -105,6 +105,18 @@ int ref_run_dt(int32_t *h, int L, int N, int D, uint64_t seed, int64_t t0, int64
 int ref_run_dt_injected(int32_t *h, int L, int N, int D, int64_t n, const int32_t *origins,
                         const int32_t *sites, int64_t *log);
 
+/* Multisurface lock-step (Sec. II; see rsos_ref.c): R realizations sharing
+ * one site sequence, each applying each selection with probability 1/2;
+ * 2 D^2 selections per tile and phase.  h holds the R lattices one after
+ * another (realization-major); log is int64[R][n][4] (t, S1, S2, A).  The
+ * injected variant runs one realization along given origins, sites (per
+ * sweep and phase, tiles of that colour in increasing tile_id, 2 D^2
+ * in-tile indices each) and coins (0/1 at the same positions). */
+int ref_run_ms(int32_t *h, int R, int L, int N, int D, uint64_t seed, int64_t t0, int64_t n,
+               int64_t *log);
+int ref_run_ms_injected(int32_t *h, int L, int N, int D, int64_t n, const int32_t *origins,
+                        const int32_t *sites, const int32_t *coins, int64_t *log);
+
 void ref_set_threads(int n);
 void ref_set_tile_order_seed(uint64_t seed);
 
