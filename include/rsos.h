@@ -202,6 +202,48 @@ rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len);
 rsos_status rsos_free(rsos_surface *s);
 
 /* --------------------------------------------------------------------- */
+/* Multisurface lock-step mode (Sec. II: multisurface coding).  Groups of  */
+/* 128 realizations of one L x L surface share the sequence of selected    */
+/* sites; each realization applies a selection with probability 1/2 (its   */
+/* own coin), which breaks the correlation between them.                   */
+/* --------------------------------------------------------------------- */
+
+typedef struct rsos_ms rsos_ms;
+
+/* Creates `groups` groups of 128 realizations, flat start, t = 0.
+ *   p       L (multiple of 16, 16 <= L <= 65536), N (N*L <= 32766), D = 8,
+ *           flags = 0, seed; group g uses the Philox key seed + g;
+ *   d_lat   caller-owned device memory of groups * L*L * 256 bytes,
+ *           16-byte aligned (NULL: the library allocates): per group and
+ *           site, 64 32-bit words; word l holds realizations 2l (low half)
+ *           and 2l+1 (high half) as 16-bit residues of their heights;
+ *   log_cap sweeps kept per realization (0 = 65536).
+ * Schedule: per sweep s, origin from Philox (0, 0, s, 2) mod 2D; colour-0
+ * then colour-1 tiles of the checkerboard; a tile makes 2 D^2 selections,
+ * selection a taking site field a of Philox (j, tile_id, s, p) as in the
+ * checkerboard layout; realization r applies it iff bit a mod 32 of word
+ * (a div 32) mod 4 of Philox (a div 128, tile_id, s, 8 + 2r + p) is set.
+ * Each realization receives L^2 attempts per sweep on average. */
+rsos_status rsos_ms_init(rsos_ms **out, const rsos_params *p, int32_t groups, uint32_t *d_lat,
+                         int64_t log_cap, void *stream);
+
+/* Enqueues n_mcs sweeps of every realization (asynchronous). */
+rsos_status rsos_ms_sweep(rsos_ms *m, int64_t n_mcs);
+
+/* Synchronises; out[g*128 + r] = record of realization r of group g at the
+ * current time (s1, s2 exact; accepted = deposits of the last sweep). */
+rsos_status rsos_ms_width(rsos_ms *m, rsos_width_t *out);
+
+/* Synchronises; records t_from .. t_from+n-1 of one realization (g*128+r). */
+rsos_status rsos_ms_log(rsos_ms *m, int32_t realization, int64_t t_from, int64_t n, rsos_width_t *out);
+
+/* Synchronises; int32 heights of one realization into host memory. */
+rsos_status rsos_ms_heights(rsos_ms *m, int32_t realization, int32_t *dst_host);
+
+/* Frees the handle and library-owned memory (never a caller's d_lat). */
+rsos_status rsos_ms_free(rsos_ms *m);
+
+/* --------------------------------------------------------------------- */
 /* Batched ensemble: many independent surfaces (any L, N, seed; one D) in   */
 /* one launch per sweep.  Independent realization sets, Sec. II.          */
 /* --------------------------------------------------------------------- */

@@ -67,6 +67,12 @@ SIGNATURES = [
     ("rsos_timing_read", c_i32, [c_vp, P(c_i64), P(ctypes.c_double), P(ctypes.c_double)]),
     ("rsos_kernel_name", c_i32, [c_vp, ctypes.c_char_p, c_i32]),
     ("rsos_free", c_i32, [c_vp]),
+    ("rsos_ms_init", c_i32, [P(c_vp), P(Params), c_i32, c_vp, c_i64, c_vp]),
+    ("rsos_ms_sweep", c_i32, [c_vp, c_i64]),
+    ("rsos_ms_width", c_i32, [c_vp, P(Width)]),
+    ("rsos_ms_log", c_i32, [c_vp, c_i32, c_i64, c_i64, P(Width)]),
+    ("rsos_ms_heights", c_i32, [c_vp, c_i32, c_vp]),
+    ("rsos_ms_free", c_i32, [c_vp]),
     ("rsos_batch_init", c_i32, [P(c_vp), c_i32, P(Params), c_vp, c_vp, P(c_i64), c_i64, c_vp]),
     ("rsos_batch_sweep", c_i32, [c_vp, P(c_i64), c_i64]),
     ("rsos_batch_width", c_i32, [c_vp, P(Width)]),

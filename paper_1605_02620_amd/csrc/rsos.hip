@@ -8,6 +8,7 @@
 #include "rsos.h"
 #include "rsos_kernels.hpp"
 #include "rsos_moments.hpp"
+#include "rsos_ms.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -1040,3 +1041,8 @@ rsos_status rsos_batch_free(rsos_batch *b)
 // serving engine (continuous batching) -- see rsos_engine.inc
 // ---------------------------------------------------------------------------
 #include "rsos_engine.inc"
+
+// ---------------------------------------------------------------------------
+// multisurface lock-step mode -- see rsos_ms.inc
+// ---------------------------------------------------------------------------
+#include "rsos_ms.inc"

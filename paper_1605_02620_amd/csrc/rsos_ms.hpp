@@ -1,0 +1,220 @@
+// rsos_ms.hpp -- gfx950 kernels of the multisurface lock-step mode.
+//
+// Multisurface coding (Sec. II): a group of 128 realizations shares one
+// sequence of selected sites; each realization applies a selection only
+// with probability 1/2 (its own coin bit), which breaks the correlation
+// between them.  On the GPU one wavefront runs one tile for the whole group:
+// lane l holds realizations 2l (low 16 bits) and 2l+1 (high 16 bits) of
+// every site as 16-bit residues, so every LDS access of a selection is 64
+// consecutive words (no bank conflicts), every global access is whole
+// 256-byte site records, and the site sequence is uniform across the wave.
+//
+// Schedule (identical bits for any launch shape): group g uses the Philox
+// key seed + g; sweep s: origin from (0, 0, s, 2) as for the checkerboard;
+// colour-0 tiles, then colour-1 tiles; a tile makes 2 D^2 selections, site
+// field a from Philox (j, tile_id, s, p) in the checkerboard layout; the coin
+// of realization r is bit a mod 32 of word (a div 32) mod 4 of Philox
+// (a div 128, tile_id, s, 8 + 2r + p).  A selection whose coin is set is an
+// RSOS attempt (Sec. I) on that realization.
+//
+// Storage: residues mod 2^16 with floor(S1_r / L^2) per realization as the
+// reference (exact while N L <= 32766, as for 16-bit single surfaces).
+#pragma once
+
+#include "rsos_kernels.hpp"
+
+namespace rsosk {
+
+constexpr int kMsReal = 128;   // realizations per group
+constexpr int kMsSlots = 8;    // accumulator spread per realization
+
+struct MsDev {
+    uint32_t *lat;        // [G][L*L][64] words (realizations 2l | 2l+1 << 16 of lane l)
+    long long *m0;        // [G][128] floor(S1 / L^2) of the current time
+    long long *acc;       // [G][128][kMsSlots][2]: (A, dS2) increments, zero between sweeps
+    long long *log;       // [G][128][log_cap][3]: (S1, S2, A) of time tau at slot tau % log_cap
+    long long *t;         // [G] sweeps done
+    long long log_cap;
+    long long t_end;
+    unsigned long long seed;
+    int L, N, T, G;
+};
+
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// signed maximum of two 16-bit lanes
+__device__ __forceinline__ uint32_t pk_max_i16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_max(__builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void ms_phase(const MsDev *__restrict__ dp, int p)
+{
+    constexpr int P = D + 2;            // padded tile side (tile plus a one-site ring)
+    constexpr int SEL = 2 * D * D;      // selections per tile
+    using TB = TileBits<D>;
+    static_assert(SEL % 128 == 0, "whole coin blocks");
+    __shared__ __attribute__((aligned(16))) uint32_t lds[P * P * 64];   // [padded site][lane]
+
+    const MsDev &d = *dp;
+    const int L = d.L, T = d.T, N = d.N;
+    const int half = T * T / 2;
+    const int g = blockIdx.x / half, k = blockIdx.x - g * half;
+    // the time is uniform: keep it (and everything derived from it, such as
+    // the site stream) in scalar registers
+    const long long tv = d.t[g];
+    const long long t = (long long)(((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(tv >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)tv));
+    if (t >= d.t_end) return;
+    const int ty = k / (T / 2), tx = 2 * (k % (T / 2)) + ((ty + p) & 1);
+    const unsigned long long key = d.seed + (unsigned long long)g;
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    const uint32_t s = (uint32_t)t;
+    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
+    const int ox = (int)(org.v[0] % (2u * D)), oy = (int)(org.v[1] % (2u * D));
+    int X0 = ox + tx * D - 1, Y0 = oy + ty * D - 1;   // global site of padded (0, 0)
+    if (X0 < 0) X0 += L;
+    if (Y0 < 0) Y0 += L;
+    if (X0 >= L) X0 -= L;
+    if (Y0 >= L) Y0 -= L;
+    const int lane = threadIdx.x;
+    const gu32 *lat = (const gu32 *)(d.lat + (size_t)g * L * L * 64);
+    gu32 *latw = (gu32 *)(d.lat + (size_t)g * L * L * 64);
+
+    // ---- load the padded tile: 4 sites per instruction, 16 lanes x 16 B per site
+#pragma unroll 4
+    for (int i = 0; i < P * P / 4; ++i) {
+        const int site = 4 * i + (lane >> 4);
+        const int sy = site / P, sx = site - sy * P;
+        int gx = X0 + sx, gy = Y0 + sy;
+        if (gx >= L) gx -= L;
+        if (gy >= L) gy -= L;
+        const v4u v = *reinterpret_cast<const gv4u *>(lat + ((size_t)gy * L + gx) * 64 + 4 * (lane & 15));
+        *reinterpret_cast<uint4 *>(&lds[site * 64 + 4 * (lane & 15)]) = make_uint4(v.x, v.y, v.z, v.w);
+    }
+    __syncthreads();
+
+    const long long m0a = d.m0[(size_t)g * kMsReal + 2 * lane];
+    const long long m0b = d.m0[(size_t)g * kMsReal + 2 * lane + 1];
+    const uint32_t m0p = ((uint32_t)m0a & 0xFFFFu) | ((uint32_t)m0b << 16);
+    const uint32_t Np = (uint32_t)N * 0x10001u;
+    const uint32_t tile_id = (uint32_t)(ty * T + tx);
+    uint32_t Ap = 0;     // accepted counts of the two realizations (16-bit lanes)
+    int qa = 0, qb = 0;  // sums of h - m0 before the accepted deposits
+
+    static_assert(SEL == 128, "one coin block per tile (D = 8)");
+    // coins of realizations 2l and 2l+1 for the tile's 128 selections
+    const u32x4 ca = philox4x32_10(0u, tile_id, s, 8u + 4u * (uint32_t)lane + (uint32_t)p, k0, k1);
+    const u32x4 cx = philox4x32_10(0u, tile_id, s, 10u + 4u * (uint32_t)lane + (uint32_t)p, k0, k1);
+    constexpr int NFULL = SEL / TB::PER, TAIL = SEL % TB::PER;
+    auto select = [&](int call, int nsel) {
+        // site fields of this call (uniform across the wave) and the coin
+        // bits of its selections, bits [call*PER, call*PER + nsel) of each
+        // realization's 128 coin bits
+        const u32x4 r = philox4x32_10((uint32_t)call, tile_id, s, (uint32_t)p, k0, k1);
+        const int b0 = call * TB::PER, lo = b0 >> 5, sh = b0 & 31;
+        const uint32_t a0 = lo == 0 ? ca.v[0] : lo == 1 ? ca.v[1] : lo == 2 ? ca.v[2] : ca.v[3];
+        const uint32_t a1 = lo == 0 ? ca.v[1] : lo == 1 ? ca.v[2] : lo == 2 ? ca.v[3] : 0u;
+        const uint32_t x0 = lo == 0 ? cx.v[0] : lo == 1 ? cx.v[1] : lo == 2 ? cx.v[2] : cx.v[3];
+        const uint32_t x1 = lo == 0 ? cx.v[1] : lo == 1 ? cx.v[2] : lo == 2 ? cx.v[3] : 0u;
+        const uint32_t cha = (uint32_t)((((unsigned long long)a1 << 32) | a0) >> sh);
+        const uint32_t chx = (uint32_t)((((unsigned long long)x1 << 32) | x0) >> sh);
+#pragma unroll
+        for (int kk = 0; kk < TB::PER; ++kk) {
+            if (kk < nsel) {
+                const uint32_t f = (r.v[kk / TB::F] >> ((kk % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
+                const int idx = ((int)(f >> TB::LOG2D) + 1) * P + (int)(f & (D - 1)) + 1;
+                const uint32_t c = lds[idx * 64 + lane];
+                const uint32_t wl = lds[(idx - 1) * 64 + lane], wr = lds[(idx + 1) * 64 + lane];
+                const uint32_t wu = lds[(idx - P) * 64 + lane], wd = lds[(idx + P) * 64 + lane];
+                // c - h_j per realization, exact in int16; accept iff every one < N
+                const uint32_t dmax = pk_max_i16(pk_max_i16(pk_sub16(c, wl), pk_sub16(c, wr)),
+                                                 pk_max_i16(pk_sub16(c, wu), pk_sub16(c, wd)));
+                const uint32_t ok = (pk_sub16(dmax, Np) >> 15) & 0x00010001u;
+                const uint32_t coin = ((cha >> kk) & 1u) | (((chx >> kk) & 1u) << 16);
+                const uint32_t acc = ok & coin;
+                lds[idx * 64 + lane] = pk_add16(c, acc);
+                Ap = pk_add16(Ap, acc);
+                const uint32_t dl = pk_sub16(c, m0p);
+                qa += (int)(int16_t)(uint16_t)dl & -(int)(acc & 1u);
+                qb += ((int)dl >> 16) & -(int)(acc >> 16);
+            }
+        }
+    };
+#pragma unroll 1
+    for (int j = 0; j < NFULL; ++j) select(j, TB::PER);
+    if constexpr (TAIL > 0) select(NFULL, TAIL);
+
+    // ---- store the tile interior: 4 sites per instruction
+#pragma unroll 4
+    for (int i = 0; i < D * D / 4; ++i) {
+        const int site = 4 * i + (lane >> 4);
+        const int sy = site / D, sx = site - sy * D;
+        int gx = X0 + 1 + sx, gy = Y0 + 1 + sy;
+        if (gx >= L) gx -= L;
+        if (gy >= L) gy -= L;
+        const uint4 v = *reinterpret_cast<const uint4 *>(&lds[((sy + 1) * P + sx + 1) * 64 + 4 * (lane & 15)]);
+        const v4u o = {v.x, v.y, v.z, v.w};
+        *reinterpret_cast<gv4u *>(latw + ((size_t)gy * L + gx) * 64 + 4 * (lane & 15)) = o;
+    }
+
+    // ---- increments of (A, S2) per realization: a deposit on h adds 2h + 1
+    const long long Aa = Ap & 0xFFFFu, Ab = Ap >> 16;
+    const long long s2a = 2 * (m0a * Aa + qa) + Aa, s2b = 2 * (m0b * Ab + qb) + Ab;
+    const int slot = (int)(tile_id & (kMsSlots - 1));
+    gu64 *acc = (gu64 *)(d.acc + (((size_t)g * kMsReal + 2 * lane) * kMsSlots + slot) * 2);
+    __hip_atomic_fetch_add(acc + 0, (unsigned long long)Aa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + 1, (unsigned long long)s2a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    acc += 2 * kMsSlots;
+    __hip_atomic_fetch_add(acc + 0, (unsigned long long)Ab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(acc + 1, (unsigned long long)s2b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Folds each realization's increments into its log, clears them, updates
+// floor(S1 / L^2) and advances the group's time.  One workgroup of 128
+// threads per group.
+__global__ __launch_bounds__(128) void ms_reduce(const MsDev *__restrict__ dp)
+{
+    const MsDev &d = *dp;
+    const int g = blockIdx.x, r = threadIdx.x;
+    const long long t = d.t[g];
+    if (t >= d.t_end) return;
+    const size_t id = (size_t)g * kMsReal + r;
+    long long *a = d.acc + id * kMsSlots * 2;
+    long long A = 0, S2 = 0;
+    for (int k = 0; k < kMsSlots; ++k) {
+        A += a[2 * k];
+        S2 += a[2 * k + 1];
+        a[2 * k] = 0;
+        a[2 * k + 1] = 0;
+    }
+    const long long *prev = d.log + (id * d.log_cap + t % d.log_cap) * 3;
+    long long *e = d.log + (id * d.log_cap + (t + 1) % d.log_cap) * 3;
+    const long long s1 = prev[0] + A;
+    e[0] = s1;
+    e[1] = prev[1] + S2;
+    e[2] = A;
+    d.m0[id] = s1 / ((long long)d.L * d.L);
+    __syncthreads();
+    if (r == 0) d.t[g] = t + 1;
+}
+
+// Realization r of group g as int32 heights (grid-stride).
+__global__ void ms_unpack(const MsDev *__restrict__ dp, int g, int r, int32_t *__restrict__ dst)
+{
+    const MsDev &d = *dp;
+    const long long n = (long long)d.L * d.L;
+    const long long m0 = d.m0[(size_t)g * kMsReal + r];
+    const uint32_t r0 = (uint32_t)m0 & 0xFFFFu;
+    const uint32_t *lat = d.lat + (size_t)g * n * 64;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const uint32_t w = lat[i * 64 + (r >> 1)];
+        const uint32_t res = (r & 1) ? (w >> 16) : (w & 0xFFFFu);
+        dst[i] = (int32_t)(m0 + (long long)(int16_t)(uint16_t)(res - r0));
+    }
+}
+
+}  // namespace rsosk

@@ -223,6 +223,61 @@ class Batch:
             pass
 
 
+class MultiSurface:
+    """Multisurface lock-step mode (rsos_ms_*): `groups` groups of 128
+    realizations of one L x L surface; the realizations of a group share
+    the sequence of selected sites and apply each selection with
+    probability 1/2.  Realization index i = 128 g + r."""
+
+    REAL = 128
+
+    def __init__(self, L: int, N: int = 1, seed: int = 0, groups: int = 1, log_cap: int = 0,
+                 device="cuda", stream=None):
+        dev = _require_gpu(device)
+        self.L, self.N, self.seed, self.groups = int(L), int(N), int(seed), int(groups)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        words = self.groups * self.L * self.L * 64
+        self.lat = torch.empty(words, dtype=torch.int32, device=dev)
+        p = _params(L, N, 8, seed)
+        self._h = ctypes.c_void_p()
+        check(lib().rsos_ms_init(ctypes.byref(self._h), ctypes.byref(p), self.groups,
+                                 ctypes.c_void_p(self.lat.data_ptr()), int(log_cap),
+                                 _stream_handle(self.stream)))
+
+    def __len__(self):
+        return self.groups * self.REAL
+
+    def sweep(self, n_mcs: int):
+        check(lib().rsos_ms_sweep(self._h, int(n_mcs)))
+        return self
+
+    def width(self) -> np.ndarray:
+        buf = (Width * len(self))()
+        check(lib().rsos_ms_width(self._h, buf))
+        return _widths(buf, len(self))
+
+    def log(self, i: int, t_from: int, n: int) -> np.ndarray:
+        buf = (Width * max(int(n), 1))()
+        check(lib().rsos_ms_log(self._h, int(i), int(t_from), int(n), buf))
+        return _widths(buf, int(n))
+
+    def heights(self, i: int) -> np.ndarray:
+        out = np.empty(self.L * self.L, dtype=np.int32)
+        check(lib().rsos_ms_heights(self._h, int(i), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if self._h:
+            check(lib().rsos_ms_free(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def philox(ctr, key):
     """The library's own Philox4x32-10 block function, run on the host."""
     c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
@@ -236,4 +291,4 @@ def w2(L, s1, s2):
     return float(lib().rsos_w2(int(L), int(s1), int(s2)))
 
 
-__all__ = ["Surface", "Batch", "philox", "w2", "LOG_DTYPE", "_lib"]
+__all__ = ["Surface", "Batch", "MultiSurface", "philox", "w2", "LOG_DTYPE", "_lib"]
