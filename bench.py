@@ -22,7 +22,11 @@ Printed JSON line (one): attempts per ns over the timed region, plus
                 as 16-bit residues (identical results, 4 B per attempt), with
                 its own roofline;
   moments       time of one exact height-distribution moment call on the
-                final state (one read of the lattice).
+                final state (one read of the lattice);
+  multisurface  the lock-step multisurface mode against the batched path on
+                the same 1024 realizations of L = 256;
+  steady_state  a reduced run of the steady-state finite-size-scaling
+                workload (L = 32..256).
 --storage packed16 makes the 16-bit surface the headline (for profiling it
 alone).
 """
@@ -173,6 +177,53 @@ def bench_batched(n_steps_batch=200):
             "batched_over_plain": round(rate_b / rate_p, 3)}
 
 
+def bench_multisurface(L=256, groups=8, sweeps=64):
+    """Multisurface lock-step mode (groups of 128 realizations sharing a site
+    sequence) against the batched path on the same realizations: aggregate
+    attempted updates per ns (L^2 attempts per realization per sweep)."""
+    import torch
+    import paper_1605_02620_amd as rsos
+    n_real = 128 * groups
+    st = torch.cuda.Stream()
+    m = rsos.MultiSurface(L, N=1, seed=1, groups=groups, log_cap=sweeps + 8, stream=st)
+    m.sweep(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.sweep(sweeps)
+    m.log(0, sweeps + 4, 1)
+    torch.cuda.synchronize()
+    t_ms = time.perf_counter() - t0
+    m.close()
+    b = rsos.Batch([(L, 1, k) for k in range(n_real)], D=8, log_cap=sweeps + 8, stream=st)
+    b.sweep(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(sweeps)
+    b.log(0, sweeps + 4, 1)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    b.close()
+    work = n_real * L * L * sweeps
+    return {"workload": f"{n_real} realizations of L={L}, N=1, D=8, {sweeps} sweeps",
+            "multisurface_attempts_per_ns": round(work / (t_ms * 1e9), 2),
+            "batched_attempts_per_ns": round(work / (t_b * 1e9), 2)}
+
+
+def bench_fss(sizes=(32, 64, 128, 256), realizations=32):
+    """Reduced steady-state finite-size-scaling run (the paper's second
+    workload at L = 32..256): aggregate rate and the fitted exponent."""
+    from paper_1605_02620_amd import fss
+    r = fss.run(sizes=sizes, N=1, realizations=realizations, start=2.0, window=4.0, moment_samples=16)
+    return {"workload": f"L in {list(sizes)}, N=1, D=8, {realizations} realizations each, "
+                        "t_start = 2 t*, window 4 t* (t* from Eq. (7) calibrated on L = 32, 64)",
+            "attempts_per_ns": round(r["attempts_per_ns"], 2), "wall_s": round(r["wall_s"], 2),
+            "alpha_fit": round(r["alpha_fit"], 4),
+            "W_sat": {int(L): round(v["W_sat"], 4) for L, v in r["sizes"].items()},
+            "S_w2": {int(L): round(v["S_w2"], 3) for L, v in r["sizes"].items()},
+            "S_h": {int(L): round(v["S_h"], 3) for L, v in r["sizes"].items()},
+            "Q_h": {int(L): round(v["Q_h"], 3) for L, v in r["sizes"].items()}}
+
+
 def bench_served(n_jobs=200, load=0.9, capacity_attempts_per_ns=None, pool_gib=8):
     """The served workload's job mix (L a power of two in [128, 8192], N in
     {1, 2, 4}, t_max log-uniform) as a Poisson stream at `load` times the
@@ -210,6 +261,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--no-packed", action="store_true", help="skip the 16-bit storage leg")
+    ap.add_argument("--no-ms", action="store_true", help="skip the multisurface leg")
+    ap.add_argument("--no-fss", action="store_true", help="skip the steady-state leg")
     ap.add_argument("--storage", choices=("int32", "packed16"), default="int32",
                     help="height storage of the headline surface")
     ap.add_argument("--copy-probe", action="store_true",
@@ -260,6 +313,10 @@ def main():
         del src, dst
     if not args.no_batch:
         out["batched"] = bench_batched()
+    if not args.no_ms:
+        out["multisurface"] = bench_multisurface()
+    if not args.no_fss:
+        out["steady_state"] = bench_fss()
     if not args.no_serve:
         # capacity of the plain path: one surface per launch at the rate the
         # single large surface reaches (the job mix's attempts are dominated
