@@ -23,6 +23,7 @@ Printed JSON line (one): attempts per ns over the timed region, plus
                 its own roofline;
   moments       time of one exact height-distribution moment call on the
                 final state (one read of the lattice);
+  double_tiling the same surface under the paper's double-tiling schedule;
   multisurface  the lock-step multisurface mode against the batched path on
                 the same 1024 realizations of L = 256;
   steady_state  a reduced run of the steady-state finite-size-scaling
@@ -92,7 +93,7 @@ def _traffic(kname, packed):
     return None
 
 
-def bench_single(L, N, D, seed, steps, warmup, packed=False):
+def bench_single(L, N, D, seed, steps, warmup, packed=False, schedule="checkerboard"):
     """K sweeps of one surface in one rsos_sweep call (hipGraph replays of
     the two kernels per sweep), then the same again with every tile-block
     kernel bracketed by HIP events on the surface's stream (graph replay
@@ -101,7 +102,7 @@ def bench_single(L, N, D, seed, steps, warmup, packed=False):
     import paper_1605_02620_amd as rsos
     stream = torch.cuda.Stream()
     s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=max(4096, steps + warmup + 1), stream=stream,
-                     packed=packed)
+                     packed=packed, schedule=schedule)
     s.sweep(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -262,6 +263,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--no-packed", action="store_true", help="skip the 16-bit storage leg")
     ap.add_argument("--no-ms", action="store_true", help="skip the multisurface leg")
+    ap.add_argument("--no-dt", action="store_true", help="skip the double-tiling leg")
     ap.add_argument("--no-fss", action="store_true", help="skip the steady-state leg")
     ap.add_argument("--storage", choices=("int32", "packed16"), default="int32",
                     help="height storage of the headline surface")
@@ -313,6 +315,14 @@ def main():
         del src, dst
     if not args.no_batch:
         out["batched"] = bench_batched()
+    if not args.no_dt:
+        # the paper's double-tiling schedule on the same surface (a different
+        # but equally valid dynamics; same 8 B per attempt)
+        dt_steps = min(args.steps, 400)
+        dtr = bench_single(L, N, D, seed, dt_steps, args.warmup, schedule="double")
+        out["double_tiling"] = {"value": round(dtr["value"], 3), "unit": "attempts/ns",
+                                "ms_per_step": round(dtr["dt"] * 1e3 / dt_steps, 4), "sweeps": dt_steps,
+                                "roofline": dtr["roofline"]}
     if not args.no_ms:
         out["multisurface"] = bench_multisurface()
     if not args.no_fss:
