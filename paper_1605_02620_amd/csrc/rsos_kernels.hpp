@@ -163,8 +163,21 @@ __device__ __forceinline__ void attempt(E *lds, int base, uint32_t f, int N, int
 {
     constexpr int LOG2D = TileBits<D>::LOG2D;
     const int idx = base + (int)(f >> LOG2D) * P + (int)(f & (D - 1));
-    const int c = lds[idx];
-    const int m = min(min((int)lds[idx - 1], (int)lds[idx + 1]), min((int)lds[idx - P], (int)lds[idx + P]));
+    int c, m;
+    if constexpr (std::is_same<E, uint8_t>::value) {
+        // unsigned byte staging (LDS-bound): the left neighbour, the site and
+        // the right neighbour from one read of the two aligned words around
+        // them (measured slower on the HBM-bound int8 path, so not used there)
+        const int a = (idx - 1) & ~3;
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(lds + a);
+        const uint32_t t3 = __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(idx - 1) & 3u);
+        const int l = (int)(t3 & 0xFFu), r = (int)((t3 >> 16) & 0xFFu);
+        c = (int)((t3 >> 8) & 0xFFu);
+        m = min(min(l, r), min((int)lds[idx - P], (int)lds[idx + P]));
+    } else {
+        c = lds[idx];
+        m = min(min((int)lds[idx - 1], (int)lds[idx + 1]), min((int)lds[idx - P], (int)lds[idx + P]));
+    }
     // h_c + 1 - h_j <= N for every neighbour j; the lower side cannot fail
     // because |h_c - h_j| <= N held before.
     int ok;
