@@ -215,8 +215,8 @@ typedef struct rsos_ms rsos_ms;
  *           flags = 0, seed; group g uses the Philox key seed + g;
  *   d_lat   caller-owned device memory of groups * L*L * 256 bytes,
  *           16-byte aligned (NULL: the library allocates): per group and
- *           site, 64 32-bit words; word l holds realizations 2l (low half)
- *           and 2l+1 (high half) as 16-bit residues of their heights;
+ *           site, 128 16-bit residues of the heights, realization r at
+ *           halfword r (a 256-byte record);
  *   log_cap sweeps kept per realization (0 = 65536).
  * Schedule: per sweep s, origin from Philox (0, 0, s, 2) mod 2D; colour-0
  * then colour-1 tiles of the checkerboard; a tile makes 2 D^2 selections,

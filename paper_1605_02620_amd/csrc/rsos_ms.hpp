@@ -3,11 +3,13 @@
 // Multisurface coding (Sec. II): a group of 128 realizations shares one
 // sequence of selected sites; each realization applies a selection only
 // with probability 1/2 (its own coin bit), which breaks the correlation
-// between them.  On the GPU one wavefront runs one tile for the whole group:
-// lane l holds realizations 2l (low 16 bits) and 2l+1 (high 16 bits) of
-// every site as 16-bit residues, so every LDS access of a selection is 64
-// consecutive words (no bank conflicts), every global access is whole
-// 256-byte site records, and the site sequence is uniform across the wave.
+// between them.  In device memory a site of a group is one 256-byte record
+// of 128 16-bit residues (realization r at halfword r).  On the GPU one
+// wavefront runs one tile for half a group, one realization per lane, with
+// the residues staged in LDS side by side: every LDS access of a selection
+// is 64 consecutive halfwords (no bank conflicts), every global access is a
+// whole 128-byte half record, and the site sequence is uniform across the
+// wave.
 //
 // Schedule (identical bits for any launch shape): group g uses the Philox
 // key seed + g; sweep s: origin from (0, 0, s, 2) as for the checkerboard;
@@ -29,7 +31,7 @@ constexpr int kMsReal = 128;   // realizations per group
 constexpr int kMsSlots = 8;    // accumulator spread per realization
 
 struct MsDev {
-    uint32_t *lat;        // [G][L*L][64] words (realizations 2l | 2l+1 << 16 of lane l)
+    uint32_t *lat;        // [G][L*L] records of 128 16-bit residues (realization r at halfword r)
     long long *m0;        // [G][128] floor(S1 / L^2) of the current time
     long long *acc;       // [G][128][kMsSlots][2]: (A, dS2) increments, zero between sweeps
     long long *log;       // [G][128][log_cap][3]: (S1, S2, A) of time tau at slot tau % log_cap
@@ -50,19 +52,25 @@ __device__ __forceinline__ uint32_t pk_max_i16(uint32_t a, uint32_t b)
                               __builtin_elementwise_max(__builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
 }
 
+// One wavefront per (group, tile of colour p, half of the group): lane l
+// runs realization r = 64 h + l.  The padded tile of the 64 realizations
+// (10 x 10 sites x 128 bytes) is staged in LDS as [site][lane] 16-bit
+// residues, so every LDS access of a selection is 64 consecutive halfwords.
 template <int D>
 __global__ __launch_bounds__(64) void ms_phase(const MsDev *__restrict__ dp, int p)
 {
     constexpr int P = D + 2;            // padded tile side (tile plus a one-site ring)
     constexpr int SEL = 2 * D * D;      // selections per tile
     using TB = TileBits<D>;
-    static_assert(SEL % 128 == 0, "whole coin blocks");
-    __shared__ __attribute__((aligned(16))) uint32_t lds[P * P * 64];   // [padded site][lane]
+    static_assert(SEL == 128, "one coin block per tile (D = 8)");
+    __shared__ __attribute__((aligned(16))) uint16_t lds[P * P * 64];   // [padded site][lane]
 
     const MsDev &d = *dp;
     const int L = d.L, T = d.T, N = d.N;
     const int half = T * T / 2;
-    const int g = blockIdx.x / half, k = blockIdx.x - g * half;
+    const int hh = (int)(blockIdx.x & 1u);
+    const int wid = (int)(blockIdx.x >> 1);
+    const int g = wid / half, k = wid - g * half;
     // the time is uniform: keep it (and everything derived from it, such as
     // the site stream) in scalar registers
     const long long tv = d.t[g];
@@ -81,66 +89,59 @@ __global__ __launch_bounds__(64) void ms_phase(const MsDev *__restrict__ dp, int
     if (X0 >= L) X0 -= L;
     if (Y0 >= L) Y0 -= L;
     const int lane = threadIdx.x;
-    const gu32 *lat = (const gu32 *)(d.lat + (size_t)g * L * L * 64);
-    gu32 *latw = (gu32 *)(d.lat + (size_t)g * L * L * 64);
+    // this half's 128 bytes of each 256-byte site record
+    const gu32 *lat = (const gu32 *)(d.lat + (size_t)g * L * L * 64) + 32 * hh;
+    gu32 *latw = (gu32 *)(d.lat + (size_t)g * L * L * 64) + 32 * hh;
 
-    // ---- load the padded tile: 4 sites per instruction, 16 lanes x 16 B per site
+    // ---- load the padded tile: 8 sites per instruction, 8 lanes x 16 B per site
 #pragma unroll 4
-    for (int i = 0; i < P * P / 4; ++i) {
-        const int site = 4 * i + (lane >> 4);
-        const int sy = site / P, sx = site - sy * P;
-        int gx = X0 + sx, gy = Y0 + sy;
-        if (gx >= L) gx -= L;
-        if (gy >= L) gy -= L;
-        const v4u v = *reinterpret_cast<const gv4u *>(lat + ((size_t)gy * L + gx) * 64 + 4 * (lane & 15));
-        *reinterpret_cast<uint4 *>(&lds[site * 64 + 4 * (lane & 15)]) = make_uint4(v.x, v.y, v.z, v.w);
+    for (int i = 0; i < (P * P + 7) / 8; ++i) {
+        const int site = 8 * i + (lane >> 3);
+        if (site < P * P) {
+            const int sy = site / P, sx = site - sy * P;
+            int gx = X0 + sx, gy = Y0 + sy;
+            if (gx >= L) gx -= L;
+            if (gy >= L) gy -= L;
+            const v4u v = *reinterpret_cast<const gv4u *>(lat + ((size_t)gy * L + gx) * 64 + 4 * (lane & 7));
+            *reinterpret_cast<uint4 *>(&lds[site * 64 + 8 * (lane & 7)]) = make_uint4(v.x, v.y, v.z, v.w);
+        }
     }
     __syncthreads();
 
-    const long long m0a = d.m0[(size_t)g * kMsReal + 2 * lane];
-    const long long m0b = d.m0[(size_t)g * kMsReal + 2 * lane + 1];
-    const uint32_t m0p = ((uint32_t)m0a & 0xFFFFu) | ((uint32_t)m0b << 16);
-    const uint32_t Np = (uint32_t)N * 0x10001u;
+    const int r = 64 * hh + lane;   // realization within the group
+    const long long m0 = d.m0[(size_t)g * kMsReal + r];
+    const uint32_t m0r = (uint32_t)m0 & 0xFFFFu;
     const uint32_t tile_id = (uint32_t)(ty * T + tx);
-    uint32_t Ap = 0;     // accepted counts of the two realizations (16-bit lanes)
-    int qa = 0, qb = 0;  // sums of h - m0 before the accepted deposits
-
-    static_assert(SEL == 128, "one coin block per tile (D = 8)");
-    // coins of realizations 2l and 2l+1 for the tile's 128 selections
-    const u32x4 ca = philox4x32_10(0u, tile_id, s, 8u + 4u * (uint32_t)lane + (uint32_t)p, k0, k1);
-    const u32x4 cx = philox4x32_10(0u, tile_id, s, 10u + 4u * (uint32_t)lane + (uint32_t)p, k0, k1);
+    int A = 0;   // accepted deposits
+    int q = 0;   // sum of h - m0 before the accepted deposits
+    // this realization's coins for the tile's 128 selections
+    const u32x4 cw = philox4x32_10(0u, tile_id, s, 8u + 2u * (uint32_t)r + (uint32_t)p, k0, k1);
     constexpr int NFULL = SEL / TB::PER, TAIL = SEL % TB::PER;
     auto select = [&](int call, int nsel) {
         // site fields of this call (uniform across the wave) and the coin
-        // bits of its selections, bits [call*PER, call*PER + nsel) of each
+        // bits of its selections, bits [call*PER, call*PER + nsel) of the
         // realization's 128 coin bits
-        const u32x4 r = philox4x32_10((uint32_t)call, tile_id, s, (uint32_t)p, k0, k1);
+        const u32x4 rr = philox4x32_10((uint32_t)call, tile_id, s, (uint32_t)p, k0, k1);
         const int b0 = call * TB::PER, lo = b0 >> 5, sh = b0 & 31;
-        const uint32_t a0 = lo == 0 ? ca.v[0] : lo == 1 ? ca.v[1] : lo == 2 ? ca.v[2] : ca.v[3];
-        const uint32_t a1 = lo == 0 ? ca.v[1] : lo == 1 ? ca.v[2] : lo == 2 ? ca.v[3] : 0u;
-        const uint32_t x0 = lo == 0 ? cx.v[0] : lo == 1 ? cx.v[1] : lo == 2 ? cx.v[2] : cx.v[3];
-        const uint32_t x1 = lo == 0 ? cx.v[1] : lo == 1 ? cx.v[2] : lo == 2 ? cx.v[3] : 0u;
-        const uint32_t cha = (uint32_t)((((unsigned long long)a1 << 32) | a0) >> sh);
-        const uint32_t chx = (uint32_t)((((unsigned long long)x1 << 32) | x0) >> sh);
+        const uint32_t w0 = lo == 0 ? cw.v[0] : lo == 1 ? cw.v[1] : lo == 2 ? cw.v[2] : cw.v[3];
+        const uint32_t w1 = lo == 0 ? cw.v[1] : lo == 1 ? cw.v[2] : lo == 2 ? cw.v[3] : 0u;
+        const uint32_t ch = (uint32_t)((((unsigned long long)w1 << 32) | w0) >> sh);
 #pragma unroll
         for (int kk = 0; kk < TB::PER; ++kk) {
             if (kk < nsel) {
-                const uint32_t f = (r.v[kk / TB::F] >> ((kk % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
+                const uint32_t f = (rr.v[kk / TB::F] >> ((kk % TB::F) * TB::B)) & (uint32_t)(D * D - 1);
                 const int idx = ((int)(f >> TB::LOG2D) + 1) * P + (int)(f & (D - 1)) + 1;
                 const uint32_t c = lds[idx * 64 + lane];
-                const uint32_t wl = lds[(idx - 1) * 64 + lane], wr = lds[(idx + 1) * 64 + lane];
-                const uint32_t wu = lds[(idx - P) * 64 + lane], wd = lds[(idx + P) * 64 + lane];
-                // c - h_j per realization, exact in int16; accept iff every one < N
-                const uint32_t dmax = pk_max_i16(pk_max_i16(pk_sub16(c, wl), pk_sub16(c, wr)),
-                                                 pk_max_i16(pk_sub16(c, wu), pk_sub16(c, wd)));
-                const uint32_t ok = (pk_sub16(dmax, Np) >> 15) & 0x00010001u;
-                const uint32_t coin = ((cha >> kk) & 1u) | (((chx >> kk) & 1u) << 16);
-                const uint32_t acc = ok & coin;
-                lds[idx * 64 + lane] = pk_add16(c, acc);
-                Ap = pk_add16(Ap, acc);
-                const uint32_t dl = pk_sub16(c, m0p);
-                qa += (int)(int16_t)(uint16_t)dl & -(int)(acc & 1u);
-                qb += ((int)dl >> 16) & -(int)(acc >> 16);
+                // c - h_j, exact in int16; accept iff every one < N
+                const int d1 = (int)(int16_t)(uint16_t)(c - lds[(idx - 1) * 64 + lane]);
+                const int d2 = (int)(int16_t)(uint16_t)(c - lds[(idx + 1) * 64 + lane]);
+                const int d3 = (int)(int16_t)(uint16_t)(c - lds[(idx - P) * 64 + lane]);
+                const int d4 = (int)(int16_t)(uint16_t)(c - lds[(idx + P) * 64 + lane]);
+                const int dm = max(max(d1, d2), max(d3, d4));
+                const int acc = (int)(((uint32_t)(dm - N) >> 31) & (ch >> kk) & 1u);
+                lds[idx * 64 + lane] = (uint16_t)(c + (uint32_t)acc);
+                A += acc;
+                q += (int)(int16_t)(uint16_t)(c - m0r) & -acc;
             }
         }
     };
@@ -148,29 +149,25 @@ __global__ __launch_bounds__(64) void ms_phase(const MsDev *__restrict__ dp, int
     for (int j = 0; j < NFULL; ++j) select(j, TB::PER);
     if constexpr (TAIL > 0) select(NFULL, TAIL);
 
-    // ---- store the tile interior: 4 sites per instruction
+    // ---- store the tile interior: 8 sites per instruction
 #pragma unroll 4
-    for (int i = 0; i < D * D / 4; ++i) {
-        const int site = 4 * i + (lane >> 4);
+    for (int i = 0; i < D * D / 8; ++i) {
+        const int site = 8 * i + (lane >> 3);
         const int sy = site / D, sx = site - sy * D;
         int gx = X0 + 1 + sx, gy = Y0 + 1 + sy;
         if (gx >= L) gx -= L;
         if (gy >= L) gy -= L;
-        const uint4 v = *reinterpret_cast<const uint4 *>(&lds[((sy + 1) * P + sx + 1) * 64 + 4 * (lane & 15)]);
+        const uint4 v = *reinterpret_cast<const uint4 *>(&lds[((sy + 1) * P + sx + 1) * 64 + 8 * (lane & 7)]);
         const v4u o = {v.x, v.y, v.z, v.w};
-        *reinterpret_cast<gv4u *>(latw + ((size_t)gy * L + gx) * 64 + 4 * (lane & 15)) = o;
+        *reinterpret_cast<gv4u *>(latw + ((size_t)gy * L + gx) * 64 + 4 * (lane & 7)) = o;
     }
 
-    // ---- increments of (A, S2) per realization: a deposit on h adds 2h + 1
-    const long long Aa = Ap & 0xFFFFu, Ab = Ap >> 16;
-    const long long s2a = 2 * (m0a * Aa + qa) + Aa, s2b = 2 * (m0b * Ab + qb) + Ab;
+    // ---- increments of (A, S2): a deposit on h adds 2h + 1
+    const long long s2 = 2 * (m0 * (long long)A + q) + A;
     const int slot = (int)(tile_id & (kMsSlots - 1));
-    gu64 *acc = (gu64 *)(d.acc + (((size_t)g * kMsReal + 2 * lane) * kMsSlots + slot) * 2);
-    __hip_atomic_fetch_add(acc + 0, (unsigned long long)Aa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(acc + 1, (unsigned long long)s2a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    acc += 2 * kMsSlots;
-    __hip_atomic_fetch_add(acc + 0, (unsigned long long)Ab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(acc + 1, (unsigned long long)s2b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gu64 *ac = (gu64 *)(d.acc + (((size_t)g * kMsReal + r) * kMsSlots + slot) * 2);
+    __hip_atomic_fetch_add(ac + 0, (unsigned long long)(long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(ac + 1, (unsigned long long)s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Folds each realization's increments into its log, clears them, updates
