@@ -54,24 +54,24 @@ constexpr int kPsGrid = 2048;       // workgroups of the power-sum reduction
 // Block-kernel variants.  The tile block shape never changes results; it
 // only has to tile the lattice: T % TX == 0, T % TY == 0, region <= L.
 // ---------------------------------------------------------------------------
-typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int, int *);
+typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int, const int *, int *);
 
 template <int D, int TX, int TY, int NT, typename E, bool FB>
-void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue)
+void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, const int *owner, int *queue)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, queue);
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, owner, queue);
 }
 
 template <int D, int TX, int TY, int NT, typename E, bool FB>
-void launch_block16(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue)
+void launch_block16(dim3 grid, hipStream_t st, const SurfDev *d, int n, const int *owner, int *queue)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, queue);
+    hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, owner, queue);
 }
 
 template <int D, int TX, int TY, int NT, typename E, bool FB>
-void launch_block_dt(dim3 grid, hipStream_t st, const SurfDev *d, int n, int *queue)
+void launch_block_dt(dim3 grid, hipStream_t st, const SurfDev *d, int n, const int *owner, int *queue)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB, 1>), grid, dim3(NT), 0, st, d, n, queue);
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB, 1>), grid, dim3(NT), 0, st, d, n, owner, queue);
 }
 
 // The double-tiling schedule is built for the domain sizes the paper
@@ -143,7 +143,11 @@ bool variant_fits(const Variant &v, int L, int N, bool packed, bool dt = false)
     const int T = L / v.D;
     const int rw = v.TX * v.D + 2 * (v.D + 1), rh = v.TY * v.D + 2 * (v.D + 1);
     const int rwl = packed ? (rw + 14) & ~7 : (rw + 6) & ~3;
-    if (T % v.TX != 0 || T % v.TY != 0 || rwl > L || rh > L) return false;
+    if (T % v.TX != 0 || T % v.TY != 0 || rh > L) return false;
+    // a region wider than the lattice only for a block as wide as the
+    // lattice (its ring columns are copies of its own far edge, recomputed
+    // from the same inputs)
+    if (rwl > L && !(v.TX * v.D == L && rwl <= 2 * L)) return false;
     // int16 staging: every staged value within 32767 of the block reference
     const bool i16_ok = (long long)N * (rw + rh + 4) + v.D * v.D <= 32767;
     // 16-bit storage: uint8 staging (N D <= 96) and the int16 fallback
@@ -341,6 +345,7 @@ struct SurfaceGroup {
     std::vector<int32_t *> readout;    // 16-bit storage: int32[L^2] device scratch per surface
     long long *d_ps = nullptr;         // power sums: per-workgroup partials, then the result
     int *d_queue = nullptr;            // blocks handed to the wider fallback launch
+    int *d_owner = nullptr;            // block -> descriptor index (several surfaces only)
     std::vector<int> lds_idx, blk_idx; // surfaces on each path
     int *d_lds_idx = nullptr;
     const Variant *variant = nullptr;
@@ -407,6 +412,17 @@ struct SurfaceGroup {
             if ((st = dev_alloc((void **)&d_queue, sizeof(int) * (1 + (size_t)total_blocks))) != RSOS_OK)
                 return st;
             HIP_TRY(hipMemset(d_queue, 0, sizeof(int)));
+            if (blk_idx.size() > 1) {
+                // owner of every block: block-path surfaces sit first in the
+                // device table, in blk_idx order
+                std::vector<int> own((size_t)total_blocks);
+                for (size_t k = 0; k < blk_idx.size(); ++k) {
+                    const SurfDev &sd = host[blk_idx[k]];
+                    for (int b = 0; b < sd.nblocks; ++b) own[(size_t)sd.block_start + b] = (int)k;
+                }
+                if ((st = dev_alloc((void **)&d_owner, sizeof(int) * own.size())) != RSOS_OK) return st;
+                HIP_TRY(hipMemcpy(d_owner, own.data(), sizeof(int) * own.size(), hipMemcpyHostToDevice));
+            }
         }
         if (!lds_idx.empty()) {
             if ((st = dev_alloc((void **)&d_lds_idx, sizeof(int) * lds_idx.size())) != RSOS_OK) return st;
@@ -484,8 +500,8 @@ struct SurfaceGroup {
         const int n = (int)blk_idx.size();
         BlockLaunch main = packed ? variant->launch16 : sched == 1 ? variant->launch_dt : variant->launch;
         BlockLaunch fb = packed ? variant->fallback16 : sched == 1 ? variant->fallback_dt : variant->fallback;
-        main(dim3(total_blocks), stream, d_desc, n, d_queue);
-        if (fb) fb(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n, d_queue);
+        main(dim3(total_blocks), stream, d_desc, n, d_owner, d_queue);
+        if (fb) fb(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n, d_owner, d_queue);
     }
 
     rsos_status enqueue_one()

@@ -320,10 +320,12 @@ __device__ __forceinline__ void store4_stream(gint32 *dst, const int4 v)
     __builtin_nontemporal_store(x, reinterpret_cast<gv4i *>(dst));
 }
 
-// Descriptor index of the surface that owns global block lb (descriptors
-// are sorted by block_start).
-__device__ __forceinline__ int find_surface(const SurfDev *descs, int nsurf, int lb)
+// Descriptor index of the surface that owns global block lb: from the
+// host-built table when there is one (one load), else by binary search over
+// the descriptors (sorted by block_start).
+__device__ __forceinline__ int find_surface(const SurfDev *descs, int nsurf, const int *owner, int lb)
 {
+    if (owner) return owner[lb];
     int lo = 0, hi = nsurf - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -486,7 +488,7 @@ struct StageLimits {
 // int8 launch.
 template <int D, int TX, int TY, int NT, typename E, bool FALLBACK, int SCHED = 0>
 __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf,
-                                                  int *__restrict__ queue)
+                                                  const int *__restrict__ owner, int *__restrict__ queue)
 {
     using G = BlockGeom<D, TX, TY>;
     using Q = typename std::conditional<sizeof(E) <= 2, int, long long>::type;
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     const int nq = FALLBACK ? queue[0] : 1;
     for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
     const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
-    const SurfDev &d = descs[find_surface(descs, nsurf, lb)];
+    const SurfDev &d = descs[find_surface(descs, nsurf, owner, lb)];
     const long long t = d.t;
     if (t >= d.t_end) continue;
 
@@ -538,6 +540,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
             if (gy >= L) gy -= L;
             int gx = gxa + 4 * cc;
             if (gx >= L) gx -= L;
+            if (gx >= L) gx -= L;  // a block as wide as the lattice: the region wraps twice
             return load4(hin + (size_t)gy * L + gx);
         };
         auto stage = [&](int i, const int4 &v) {
@@ -600,6 +603,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         const int kslot = (off >> 2) + slot;  // LDS chunk index of this thread
         int gc = gxa + 4 * kslot;
         if (gc >= L) gc -= L;
+        if (gc >= L) gc -= L;
         const bool partial = slot == 0 && m != 0;
         // chunks whose 128-byte line lies wholly inside the block row are
         // streamed past the caches; lines shared with the neighbouring block
@@ -639,6 +643,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         if (m != 0) {
             const int kt = (off >> 2) + SPR;
             int gct = gxa + 4 * kt;
+            if (gct >= L) gct -= L;
             if (gct >= L) gct -= L;
             for (int r = threadIdx.x; r < G::BH; r += NT) {
                 int gy = gy0 + G::RING + r;
@@ -736,7 +741,7 @@ template <> struct Stage16<int16_t> {
 // the int16 fallback.
 template <int D, int TX, int TY, int NT, typename E, bool FALLBACK, int SCHED = 0>
 __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ descs, int nsurf,
-                                                    int *__restrict__ queue)
+                                                    const int *__restrict__ owner, int *__restrict__ queue)
 {
     using G = BlockGeom<D, TX, TY, 8>;
     using S = Stage16<E>;
@@ -751,7 +756,7 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
     const int nq = FALLBACK ? queue[0] : 1;
     for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
     const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
-    const SurfDev &d = descs[find_surface(descs, nsurf, lb)];
+    const SurfDev &d = descs[find_surface(descs, nsurf, owner, lb)];
     const long long t = d.t;
     if (t >= d.t_end) continue;
 
@@ -787,6 +792,7 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
             int gy = gy0 + r;
             if (gy >= L) gy -= L;
             int gx = gxa + 8 * cc;
+            if (gx >= L) gx -= L;
             if (gx >= L) gx -= L;
             return *reinterpret_cast<const gv4u *>(hin + (size_t)gy * L + gx);
         };
@@ -850,6 +856,7 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
         const int kslot = (off >> 3) + slot;
         int gc = gxa + 8 * kslot;
         if (gc >= L) gc -= L;
+        if (gc >= L) gc -= L;
         const bool partial = slot == 0 && m != 0;
         // byte offsets within the row; rows are 128-byte aligned when L % 64 == 0
         const int row_lo = 2 * (gxa + off), row_hi = row_lo + 2 * G::BW;
@@ -882,6 +889,7 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
         if (m != 0) {
             const int kt = (off >> 3) + SPR;
             int gct = gxa + 8 * kt;
+            if (gct >= L) gct -= L;
             if (gct >= L) gct -= L;
             for (int r = threadIdx.x; r < G::BH; r += NT) {
                 int gy = gy0 + G::RING + r;
