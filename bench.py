@@ -148,8 +148,11 @@ def bench_batched(n_steps_batch=200):
     ens = workloads.cfg_ensemble()
     specs = [(s.L, s.N, s.seed) for s in ens]
     total_sites = sum(L * L for (L, _, _) in specs)
+    # warm-ups of 64 sweeps also build the graphs that the timed sweeps
+    # replay, for both modes
+    warm = 64
     b = rsos.Batch(specs, D=8, log_cap=4096, stream=torch.cuda.Stream())
-    b.sweep(4)
+    b.sweep(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.sweep(n_steps_batch)
@@ -161,7 +164,7 @@ def bench_batched(n_steps_batch=200):
     st = torch.cuda.Stream()
     surfs = [rsos.Surface(L, N=N, seed=sd, D=8, log_cap=4096, stream=st) for (L, N, sd) in specs]
     for s in surfs:
-        s.sweep(4)
+        s.sweep(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in surfs:
@@ -186,21 +189,23 @@ def bench_multisurface(L=256, groups=8, sweeps=64):
     import paper_1605_02620_amd as rsos
     n_real = 128 * groups
     st = torch.cuda.Stream()
-    m = rsos.MultiSurface(L, N=1, seed=1, groups=groups, log_cap=sweeps + 8, stream=st)
-    m.sweep(4)
+    # the warm-up also builds the graphs the timed sweeps replay
+    warm = 64
+    m = rsos.MultiSurface(L, N=1, seed=1, groups=groups, log_cap=sweeps + warm + 8, stream=st)
+    m.sweep(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.sweep(sweeps)
-    m.log(0, sweeps + 4, 1)
+    m.log(0, sweeps + warm, 1)
     torch.cuda.synchronize()
     t_ms = time.perf_counter() - t0
     m.close()
-    b = rsos.Batch([(L, 1, k) for k in range(n_real)], D=8, log_cap=sweeps + 8, stream=st)
-    b.sweep(4)
+    b = rsos.Batch([(L, 1, k) for k in range(n_real)], D=8, log_cap=sweeps + warm + 8, stream=st)
+    b.sweep(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.sweep(sweeps)
-    b.log(0, sweeps + 4, 1)
+    b.log(0, sweeps + warm, 1)
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     b.close()
@@ -257,7 +262,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")

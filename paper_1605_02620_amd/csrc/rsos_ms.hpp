@@ -29,7 +29,7 @@
 namespace rsosk {
 
 constexpr int kMsReal = 128;    // realizations per group
-constexpr int kMsChunks = 128;  // most tile ranges summed in the first reduction step
+constexpr int kMsChunks = 256;  // most tile ranges summed in the first reduction step
 
 struct MsDev {
     uint32_t *lat;        // [G][L*L] records of 128 16-bit residues (realization r at halfword r)
@@ -306,45 +306,75 @@ __global__ __launch_bounds__(128) void ms_phase_b(const MsDev *__restrict__ dp, 
     ms_record(d, g, tile_id, r, A, q + dref * A);
 }
 
-// First reduction step after both phases: workgroup (c, g) sums the tile
-// records of tile range c of group g for each of its 128 realizations.
-__global__ __launch_bounds__(128) void ms_partial(const MsDev *__restrict__ dp)
+// The sums over tiles run in two steps, each a workgroup of kMsSub x 128
+// threads: thread (sub, r) adds every kMsSub-th value for realization r
+// (independent loads, unrolled, so the loads overlap), then the kMsSub
+// partial sums are combined in LDS.
+constexpr int kMsSub = 4;
+
+__device__ __forceinline__ void ms_combine(long long &A, long long &H)
+{
+    __shared__ long long sa[kMsSub][kMsReal], sh[kMsSub][kMsReal];
+    const int sub = threadIdx.x / kMsReal, r = threadIdx.x % kMsReal;
+    sa[sub][r] = A;
+    sh[sub][r] = H;
+    __syncthreads();
+    if (sub == 0) {
+#pragma unroll
+        for (int k = 1; k < kMsSub; ++k) {
+            A += sa[k][r];
+            H += sh[k][r];
+        }
+    }
+}
+
+// First step after both phases: workgroup (c, g) sums the tile records of
+// tile range c of group g for each of its 128 realizations.
+__global__ __launch_bounds__(kMsSub * kMsReal) void ms_partial(const MsDev *__restrict__ dp)
 {
     const MsDev &d = *dp;
-    const int c = blockIdx.x, g = blockIdx.y, r = threadIdx.x;
+    const int c = blockIdx.x, g = blockIdx.y;
+    const int sub = threadIdx.x / kMsReal, r = threadIdx.x % kMsReal;
     if (d.t[g] >= d.t_end) return;
     const long long tiles = (long long)d.T * d.T;
     const long long cs = (tiles + d.nchunk - 1) / d.nchunk;
     const long long lo = c * cs, hi = min(tiles, lo + cs);
     const int *p = d.part + (size_t)g * tiles * kMsReal + r;
     long long A = 0, H = 0;
-#pragma unroll 8
-    for (long long k = lo; k < hi; ++k) {
+#pragma unroll 16
+    for (long long k = lo + sub; k < hi; k += kMsSub) {
         const int v = p[k * kMsReal];
         A += v & 255;
         H += v >> 8;
     }
-    long long *o = d.chunk + (((size_t)g * d.nchunk + c) * kMsReal + r) * 2;
-    o[0] = A;
-    o[1] = H;
+    ms_combine(A, H);
+    if (sub == 0) {
+        long long *o = d.chunk + (((size_t)g * d.nchunk + c) * kMsReal + r) * 2;
+        o[0] = A;
+        o[1] = H;
+    }
 }
 
-// Folds each realization's sweep (A, H) into its log (a deposit on height
-// h adds 2h + 1 to S2, and h = m0 + (h - m0)), updates floor(S1 / L^2) and
-// advances the group's time.  One workgroup of 128 threads per group.
-__global__ __launch_bounds__(128) void ms_reduce(const MsDev *__restrict__ dp)
+// Second step: folds each realization's sweep (A, H) into its log (a
+// deposit on height h adds 2h + 1 to S2, and h = m0 + (h - m0)), updates
+// floor(S1 / L^2) and advances the group's time.  One workgroup per group.
+__global__ __launch_bounds__(kMsSub * kMsReal) void ms_reduce(const MsDev *__restrict__ dp)
 {
     const MsDev &d = *dp;
-    const int g = blockIdx.x, r = threadIdx.x;
+    const int g = blockIdx.x;
+    const int sub = threadIdx.x / kMsReal, r = threadIdx.x % kMsReal;
     const long long t = d.t[g];
     if (t >= d.t_end) return;
     const size_t id = (size_t)g * kMsReal + r;
     long long A = 0, H = 0;
-    for (int c = 0; c < d.nchunk; ++c) {
+#pragma unroll 16
+    for (int c = sub; c < d.nchunk; c += kMsSub) {
         const long long *o = d.chunk + (((size_t)g * d.nchunk + c) * kMsReal + r) * 2;
         A += o[0];
         H += o[1];
     }
+    ms_combine(A, H);
+    if (sub != 0) return;
     const long long S2 = 2 * (d.m0[id] * A + H) + A;
     const long long *prev = d.log + (id * d.log_cap + t % d.log_cap) * 3;
     long long *e = d.log + (id * d.log_cap + (t + 1) % d.log_cap) * 3;
@@ -353,7 +383,7 @@ __global__ __launch_bounds__(128) void ms_reduce(const MsDev *__restrict__ dp)
     e[1] = prev[1] + S2;
     e[2] = A;
     d.m0[id] = s1 / ((long long)d.L * d.L);
-    __syncthreads();
+    // every thread read t before the combine barrier
     if (r == 0) d.t[g] = t + 1;
 }
 
