@@ -200,19 +200,23 @@ def bench_multisurface(L=256, groups=8, sweeps=64):
     torch.cuda.synchronize()
     t_ms = time.perf_counter() - t0
     m.close()
-    b = rsos.Batch([(L, 1, k) for k in range(n_real)], D=8, log_cap=sweeps + warm + 8, stream=st)
-    b.sweep(warm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.sweep(sweeps)
-    b.log(0, sweeps + warm, 1)
-    torch.cuda.synchronize()
-    t_b = time.perf_counter() - t0
-    b.close()
+    t_b = {}
+    for packed in (False, True):
+        b = rsos.Batch([(L, 1, k) for k in range(n_real)], D=8, log_cap=sweeps + warm + 8, stream=st,
+                       packed=packed)
+        b.sweep(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.sweep(sweeps)
+        b.log(0, sweeps + warm, 1)
+        torch.cuda.synchronize()
+        t_b[packed] = time.perf_counter() - t0
+        b.close()
     work = n_real * L * L * sweeps
     return {"workload": f"{n_real} realizations of L={L}, N=1, D=8, {sweeps} sweeps",
             "multisurface_attempts_per_ns": round(work / (t_ms * 1e9), 2),
-            "batched_attempts_per_ns": round(work / (t_b * 1e9), 2)}
+            "batched_attempts_per_ns": round(work / (t_b[False] * 1e9), 2),
+            "batched_packed16_attempts_per_ns": round(work / (t_b[True] * 1e9), 2)}
 
 
 def bench_fss(sizes=(32, 64, 128, 256), realizations=32):
