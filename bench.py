@@ -78,17 +78,24 @@ def cpu_baseline(L, N, D, seed, budget_s=12.0):
                       f"{dt:.1f} s, OpenMP over the tiles of a phase"}
 
 
-def _traffic(kname, packed):
+def _traffic(kname, packed, schedule="checkerboard"):
     """Measured HBM bytes per launch from the committed counter summary, only
     while it describes this kernel source and instance."""
     from paper_1605_02620_amd import profiling
-    name = "block_sweep16_traffic.json" if packed else "block_sweep_traffic.json"
+    if schedule == "double":
+        name = "block_sweep_dt_traffic.json"
+    else:
+        name = "block_sweep16_traffic.json" if packed else "block_sweep_traffic.json"
     tr = profiling.current_traffic(os.path.join(ROOT, "profiles", name))
     rk = (tr or {}).get("kernel", "").replace(" ", "")
     for a, b in ((",unsignedchar,", ",uint8,"), (",signedchar,", ",int8,"), (",short,", ",int16,"),
                  (",int,", ",int32,")):
         rk = rk.replace(a, b)
-    if tr is not None and rk.startswith("voidrsosk::" + kname[:-1] + ","):
+    # kernel_name() appends ",dt" for the double-tiling instance, whose last
+    # template argument (the schedule) is 1
+    dt = kname.endswith(",dt>")
+    base = kname[:-4] if dt else kname[:-1]
+    if tr is not None and rk.startswith("voidrsosk::" + base + ",") and (",1>(" in rk) == dt:
         return tr["traffic_bytes_per_launch"]
     return None
 
@@ -130,7 +137,7 @@ def bench_single(L, N, D, seed, steps, warmup, packed=False, schedule="checkerbo
     achieved = L * L * bpa / (mean_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": _traffic(kname, packed), "traffic_unit": "bytes per launch",
+                "traffic": _traffic(kname, packed, schedule), "traffic_unit": "bytes per launch",
                 "kernel": kname, "launches_timed": launches, "kernel_mean_ms": round(mean_ms, 4),
                 "algorithmic_bytes_per_launch": L * L * bpa}
     moments = {"ms_per_call": round(mom_ms, 4),
@@ -276,6 +283,8 @@ def main():
     ap.add_argument("--no-fss", action="store_true", help="skip the steady-state leg")
     ap.add_argument("--storage", choices=("int32", "packed16"), default="int32",
                     help="height storage of the headline surface")
+    ap.add_argument("--schedule", choices=("checkerboard", "double"), default="checkerboard",
+                    help="tile schedule of the headline surface (the double-tiling leg uses 'double')")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -289,7 +298,8 @@ def main():
 
     cfg = workloads.cfg_single()
     L, N, D, seed = cfg.L, cfg.N, cfg.D, cfg.seed
-    head = bench_single(L, N, D, seed, args.steps, args.warmup, packed=args.storage == "packed16")
+    head = bench_single(L, N, D, seed, args.steps, args.warmup, packed=args.storage == "packed16",
+                        schedule=args.schedule)
     value, dt, w, roofline = head["value"], head["dt"], head["w"], head["roofline"]
     out = {"metric": "attempted site updates/ns", "value": round(value, 3),
            "unit": "attempts/ns", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -299,10 +309,10 @@ def main():
                                   f"start, seed {seed}, {args.steps} sweeps timed after "
                                   f"{args.warmup} warm-up sweeps",
                       "L": L, "N": N, "D": D, "seed": seed, "sweeps": args.steps,
-                      "storage": args.storage,
+                      "storage": args.storage, "schedule": args.schedule,
                       "final_t": int(w["t"]), "final_w2": float(w["w2"])},
            "roofline": roofline, "moments": head["moments"]}
-    if args.storage == "int32" and not args.no_packed:
+    if args.storage == "int32" and args.schedule == "checkerboard" and not args.no_packed:
         # the same surface and sweeps with heights kept as 16-bit residues
         # (identical results; 4 B per attempt)
         pk = bench_single(L, N, D, seed, args.steps, args.warmup, packed=True)
