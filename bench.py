@@ -226,7 +226,7 @@ def bench_multisurface(L=256, groups=8, sweeps=64):
             "batched_packed16_attempts_per_ns": round(work / (t_b[True] * 1e9), 2)}
 
 
-def bench_fss(sizes=(32, 64, 128, 256), realizations=32):
+def bench_fss(sizes=(32, 64, 128, 256), realizations=256):
     """Reduced steady-state finite-size-scaling run (the paper's second
     workload at L = 32..256): aggregate rate and the fitted exponent."""
     from paper_1605_02620_amd import fss
