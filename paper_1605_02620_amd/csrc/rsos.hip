@@ -124,7 +124,7 @@ struct Variant {
 const Variant kVariants[] = {
     V16P(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
     V16P(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64),
-    V8(8, 32, 8, 192), V8W(8, 32, 8, 192), V16P(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
+    V8(8, 32, 8, 256), V8W(8, 32, 8, 256), V16P(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
     V32(8, 8, 8, 64), V32(8, 2, 2, 64),
     V16P(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
 };
