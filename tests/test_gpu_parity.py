@@ -174,6 +174,28 @@ def test_full_size_first_sweeps(rsos, oracle):
     _compare(g_log, r_log, g_h, r_h, L)
 
 
+def test_max_size_first_sweeps(rsos, oracle):
+    """The largest lattice the library accepts, L = 65536 (2^32 sites, 16 GiB
+    per int32 buffer; every site index needs 64 bits on both sides): the
+    first sweep from the flat start, every site and every sum."""
+    L, N, D, seed, n = 65536, 1, 8, 21, 1
+    _say(f"maximum size L={L} first {n} sweeps")
+    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=8)
+    s.sweep(n)
+    g_log = s.log(1, n)
+    g_h = s.heights()
+    s.close()
+    del s
+    _say("maximum size: oracle")
+    h = workloads.flat(L)
+    oracle.set_threads(16)
+    try:
+        r_log = oracle.run(h, L, N, D, seed=seed, t0=0, n=n)
+    finally:
+        oracle.set_threads(0)
+    _compare(g_log, r_log, g_h, h, L)
+
+
 def test_full_size_invariants(rsos):
     """2000 sweeps of the 16384^2 surface: the restriction holds everywhere,
     S1 equals the accepted-deposit ledger, and S2 matches the heights."""
