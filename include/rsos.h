@@ -63,7 +63,7 @@ typedef enum {
 /* Parameters of one surface.
  *   L     lattice side, a multiple of 2*D, 2*D <= L <= 65536;
  *   N     step restriction of Sec. I, N >= 1 (INT32_MAX: no restriction);
- *   D     tile side of the domain decomposition, one of 2, 4, 8, 16
+ *   D     tile side of the domain decomposition, one of 2, 4, 8, 16, 32
  *         (the paper uses 8 x 8 domains, Sec. II, and tests 16 x 16,
  *         Sec. III.C); part of the result;
  *   flags 0, RSOS_FLAG_PACKED16 (storage only: results are identical) or

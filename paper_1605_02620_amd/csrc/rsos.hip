@@ -127,6 +127,7 @@ const Variant kVariants[] = {
     V8(8, 32, 8, 256), V8W(8, 32, 8, 256), V16P(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
     V32(8, 8, 8, 64), V32(8, 2, 2, 64),
     V16P(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
+    V8(32, 2, 2, 64), V32(32, 2, 2, 64),
 };
 #undef P16
 #undef DT
@@ -216,16 +217,17 @@ LdsLaunch lds_launcher(int D, int sched = 0)
     case 4: return launch_lds<4, 0>;
     case 8: return launch_lds<8, 0>;
     case 16: return launch_lds<16, 0>;
+    case 32: return launch_lds<32, 0>;
     }
     return nullptr;
 }
 
-bool valid_D(int D) { return D == 2 || D == 4 || D == 8 || D == 16; }
+bool valid_D(int D) { return D == 2 || D == 4 || D == 8 || D == 16 || D == 32; }
 
 rsos_status check_params(const rsos_params *p)
 {
     if (!p) return fail(RSOS_E_INVAL, "params is NULL");
-    if (!valid_D(p->D)) return fail(RSOS_E_INVAL, "D=%d: must be 2, 4, 8 or 16", p->D);
+    if (!valid_D(p->D)) return fail(RSOS_E_INVAL, "D=%d: must be 2, 4, 8, 16 or 32", p->D);
     if (p->L < 2 * p->D || p->L > 65536 || p->L % (2 * p->D) != 0)
         return fail(RSOS_E_INVAL, "L=%d: must be a multiple of 2D=%d in [2D, 65536]", p->L, 2 * p->D);
     if (p->N < 1) return fail(RSOS_E_INVAL, "N=%d: must be >= 1", p->N);

@@ -120,6 +120,13 @@ def test_parameter_checks_without_gpu(so):
     assert st == _lib.E_INVAL and "tile-block" in msg
     # valid parameters get as far as the NULL buffer check
     for (L, N, D) in [(16384, 1, 8), (8192, 3, 8), (4096, 7, 8), (1024, 12, 8), (256, 1, 8), (512, 3, 16),
-                      (256, 1, 2), (256, 2, 4)]:
+                      (256, 1, 2), (256, 2, 4), (256, 2, 32)]:
         st, msg = init(L, N, D, _lib.FLAG_PACKED16)
         assert st == _lib.E_INVAL and "d_h" in msg, (L, N, D, msg)
+    # the tile sides: 2, 4, 8, 16, 32; L a multiple of 2 D
+    for (L, D) in [(64, 32), (192, 32), (65536, 32), (4, 2)]:
+        st, msg = init(L, 1, D, 0)
+        assert st == _lib.E_INVAL and "d_h" in msg, (L, D, msg)
+    for (L, D) in [(64, 3), (64, 64), (96, 32), (32, 32), (131072, 8)]:
+        st, msg = init(L, 1, D, 0)
+        assert st == _lib.E_INVAL and ("D=" in msg or "L=" in msg), (L, D, msg)

@@ -62,6 +62,7 @@ CASES = [
     (2048, 1, 8, 37, 70, "flat"),       # 70 sweeps: two hipGraph replays
     (768, 2, 8, 47, 20, "high"),        # heights straddle 3 * 2^16
     (256, 1, 8, 53, 20, "top"),         # heights near 170 * 2^16 (near the S2 limit at L = 256)
+    (256, 2, 32, 59, 6, "rough"),       # D = 32: 2x2 tile blocks
 ]
 
 

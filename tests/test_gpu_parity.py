@@ -63,6 +63,9 @@ CASES = [
     (256, 1, 2, 29, 10, "flat"),
     (256, 2 ** 31 - 1, 8, 31, 6, "flat"),  # no restriction: every attempt accepted
     (2048, 1, 8, 37, 60, "flat"),      # 256 blocks per sweep
+    (64, 1, 32, 41, 40, "flat"),       # D = 32: LDS path
+    (256, 2, 32, 43, 6, "rough"),      # D = 32: 2x2 tile blocks, int8 staging
+    (192, 5, 32, 47, 4, "rough"),      # D = 32, N D = 160: int32 staging
 ]
 
 

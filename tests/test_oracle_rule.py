@@ -20,6 +20,7 @@ INT32_MAX = 2 ** 31 - 1
 @pytest.mark.parametrize("L,D,N,sweeps,start", [
     (4, 2, 1, 3, "flat"), (8, 2, 1, 4, "rough"), (8, 4, 2, 3, "rough"),
     (16, 8, 1, 3, "flat"), (32, 8, 1, 2, "rough"), (32, 16, 3, 2, "rough"),
+    (64, 32, 2, 2, "rough"),
 ])
 def test_injected_path_matches_python_rule(oracle, L, D, N, sweeps, start):
     rng = np.random.default_rng(L * 100 + D * 10 + N)
@@ -65,7 +66,7 @@ def test_single_attempt_rule_by_hand(oracle):
     assert oracle.attempt(h, L, 2, 3, 0) == 1   # allowed with N = 2
 
 
-@pytest.mark.parametrize("L,N,D", [(32, 1, 8), (64, 2, 8), (48, 1, 4), (64, 4, 16)])
+@pytest.mark.parametrize("L,N,D", [(32, 1, 8), (64, 2, 8), (48, 1, 4), (64, 4, 16), (128, 2, 32)])
 def test_invariants_every_sweep(oracle, L, N, D):
     """RSOS restriction after every sweep; S1(t) = S1(0) + accepted; S1 and S2
     equal sums recomputed from the heights; 0 < A <= L^2."""
