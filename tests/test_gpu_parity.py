@@ -147,6 +147,38 @@ def test_batch_matches_solo_oracle(rsos, oracle):
         assert b.width()[i]["t"] == n + 2
 
 
+def test_empty_work(rsos, oracle):
+    """Zero-sweep calls change nothing (single surface, and surfaces given 0
+    sweeps inside a batch next to surfaces that advance, on both the tile-
+    block and the LDS paths); the work that follows is still bit-exact."""
+    _say("empty work")
+    L, N, seed = 256, 1, 61
+    s = rsos.Surface(L, N=N, seed=seed, D=8)
+    s.sweep(0).sweep(0)
+    w = s.width()
+    assert (w["t"], w["s1"], w["s2"], w["accepted"]) == (0, 0, 0, 0)
+    assert not s.heights().any()
+    s.sweep(3).sweep(0)
+    r_h, r_log = _oracle_run(oracle, workloads.flat(L), L, N, 8, seed, 0, 3)
+    _compare(s.log(1, 3), r_log, s.heights(), r_h, L)
+    s.close()
+    specs = [(256, 1, 62), (64, 1, 63), (512, 2, 64), (128, 1, 65)]
+    counts = [0, 5, 0, 4]
+    b = rsos.Batch(specs, D=8)
+    b.sweep(counts)
+    ws = b.width()
+    for i, ((Lb, Nb, sb), n) in enumerate(zip(specs, counts)):
+        assert ws[i]["t"] == n
+        if n == 0:
+            assert not b.heights(i).any() and ws[i]["s1"] == 0
+        else:
+            r_h, r_log = _oracle_run(oracle, workloads.flat(Lb), Lb, Nb, 8, sb, 0, n)
+            _compare(b.log(i, 1, n), r_log, b.heights(i), r_h, Lb)
+    b.sweep([0, 0, 0, 0])
+    assert [int(x) for x in b.width()["t"]] == counts
+    b.close()
+
+
 def test_invalid_arguments(rsos):
     from paper_1605_02620_amd._lib import RsosError, E_INVAL, E_RSOS
     _say("invalid arguments")
