@@ -218,6 +218,8 @@ typedef struct rsos_ms rsos_ms;
  *           site, 128 16-bit residues of the heights, realization r at
  *           halfword r (a 256-byte record);
  *   log_cap sweeps kept per realization (0 = 65536).
+ * Besides the log (128 * log_cap * 24 bytes per group) the library owns
+ * 8 * L*L bytes per group of per-tile partial sums.
  * Schedule: per sweep s, origin from Philox (0, 0, s, 2) mod 2D; colour-0
  * then colour-1 tiles of the checkerboard; a tile makes 2 D^2 selections,
  * selection a taking site field a of Philox (j, tile_id, s, p) as in the
