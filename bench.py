@@ -351,6 +351,9 @@ def main():
         # single large surface reaches (the job mix's attempts are dominated
         # by its largest lattices)
         out["served"] = bench_served(capacity_attempts_per_ns=value)
+        half = bench_served(load=0.5, capacity_attempts_per_ns=value)
+        out["served"]["at_half_load"] = {k: half[k] for k in ("jobs_done", "wall_s", "attempts_per_ns",
+                                                              "latency_p50_s", "latency_p99_s")}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, N, D, seed)
     print(json.dumps(out), flush=True)
