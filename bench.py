@@ -71,11 +71,28 @@ def cpu_baseline(L, N, D, seed, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s or sweeps >= 64:
             break
     dt = time.perf_counter() - t0
+    # one thread, on the first sweeps of a smaller lattice of the same kind
+    # (the per-attempt cost does not depend on L once the lattice outgrows
+    # the caches)
+    L1 = 4096
+    ref.set_threads(1)
+    h1 = workloads.flat(L1)
+    n1 = 0
+    t1 = time.perf_counter()
+    while True:
+        ref.run(h1, L1, N, D, seed=seed, t0=n1, n=1, log=False)
+        n1 += 1
+        if time.perf_counter() - t1 > budget_s / 4 or n1 >= 16:
+            break
+    dt1 = time.perf_counter() - t1
     ref.set_threads(0)
     return {"value": round(sweeps * L * L / (dt * 1e9), 4), "unit": "attempted site updates/ns",
             "cores": threads, "kind": "oracle",
             "sample": f"first {sweeps} sweeps of the L={L} N={N} D={D} surface from flat, "
-                      f"{dt:.1f} s, OpenMP over the tiles of a phase"}
+                      f"{dt:.1f} s, OpenMP over the tiles of a phase",
+            "single_thread": {"value": round(n1 * L1 * L1 / (dt1 * 1e9), 4), "cores": 1,
+                              "sample": f"first {n1} sweeps of an L={L1} N={N} D={D} surface "
+                                        f"from flat, {dt1:.1f} s"}}
 
 
 def _traffic(kname, packed, schedule="checkerboard"):
