@@ -56,14 +56,6 @@ __device__ __forceinline__ void ms_record(const MsDev &d, int g, uint32_t tile_i
 }
 
 typedef __attribute__((address_space(1))) uint32_t gu32;
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-
-// signed maximum of two 16-bit lanes
-__device__ __forceinline__ uint32_t pk_max_i16(uint32_t a, uint32_t b)
-{
-    return __builtin_bit_cast(uint32_t,
-                              __builtin_elementwise_max(__builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
-}
 
 // One wavefront per (group, tile of colour p, half of the group): lane l
 // runs realization r = 64 h + l.  The padded tile of the 64 realizations
