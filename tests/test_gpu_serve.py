@@ -103,3 +103,29 @@ def test_poisson_stream_summary(pkg):
     assert summ["jobs_done"] == len(jobs)
     assert 0 < summ["latency_p50_s"] <= summ["latency_p99_s"]
     eng.close()
+
+
+@pytest.mark.parametrize("D,jobs", [
+    (16, [(256, 1, 41, 20), (64, 2, 42, 30), (512, 3, 43, 8), (128, 1, 44, 12)]),
+    (32, [(256, 2, 45, 6), (64, 1, 46, 10), (192, 5, 47, 4)]),
+])
+def test_engine_other_tile_sides(pkg, oracle, D, jobs):
+    """Engines whose jobs use D = 16 or 32: every job equals the oracle."""
+    rsos, serve = pkg
+    _say(f"engine D={D}")
+    eng = serve.Engine(pool_bytes=64 << 20, max_running=8, D=D)
+    ids = [eng.submit(L, N, s, tm, [tm], keep_heights=True) for (L, N, s, tm) in jobs]
+    for _ in range(200):
+        eng.step(16)
+        if eng.stats()["finished"] == len(jobs):
+            break
+    assert eng.stats()["finished"] == len(jobs)
+    for jid, (L, N, s, tm) in zip(ids, jobs):
+        samples, h, _ = eng.result(jid, heights=True)
+        ref_h = workloads.flat(L)
+        r_log = oracle.run(ref_h, L, N, D, seed=s, t0=0, n=tm)
+        assert np.array_equal(h, ref_h), (D, L, N, s)
+        rec = samples[0]
+        assert int(rec["t"]) == tm
+        assert (rec["s1"], rec["s2"], rec["accepted"]) == tuple(int(x) for x in r_log[tm - 1, 1:])
+    eng.close()
