@@ -1,6 +1,7 @@
-"""Host logic of the measurement (no GPU): bench.py's refusal of more than
-one GPU, the traffic summary's counter scaling, and the matching of a stored
-summary to the kernel instance bench.py reports."""
+"""Host logic (no GPU): bench.py's refusal of more than one GPU, the traffic
+summary's counter scaling, the matching of a stored summary to the kernel
+instance bench.py reports, and the package's refusal to run without a GPU or
+without its library."""
 import csv
 import json
 import os
@@ -87,3 +88,23 @@ def test_committed_summaries_describe_current_source():
         d = json.load(open(os.path.join(ROOT, "profiles", name)))
         assert d["kernel_source_sha256_16"] == profiling.kernel_hash(), name
         assert profiling.current_traffic(os.path.join(ROOT, "profiles", name)) is not None
+
+
+def test_no_cpu_fallback():
+    """Without a GPU every entry of the Python package refuses to run, and
+    without the built library the binding raises instead of computing."""
+    import pytest
+    import torch
+    import paper_1605_02620_amd as pkg
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1605_02620_amd import serve
+    for make in (lambda: pkg.Surface(64, N=1, D=8), lambda: pkg.Batch([(64, 1, 1)], D=8),
+                 lambda: pkg.MultiSurface(16, N=1, seed=1, groups=1), lambda: serve.Engine(1 << 20)):
+        with pytest.raises(RuntimeError, match="no CPU fallback"):
+            make()
+    code = ("import os; os.environ['RSOS_LIBRARY'] = '/nonexistent/librsos.so'\n"
+            "from paper_1605_02620_amd import _lib\n"
+            "try:\n    _lib.lib()\nexcept ImportError as e:\n    print('refused:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("refused:"), (r.stdout, r.stderr)
