@@ -46,6 +46,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_ATTEMPT = 8  # int32 read + write per site per sweep
 
 
+def _progress(msg):
+    """One line per finished leg on stderr (the JSON result line is stdout's
+    only line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _cores():
     try:
         return len(os.sched_getaffinity(0))
@@ -59,6 +65,8 @@ def cpu_baseline(L, N, D, seed, budget_s=12.0):
     import numpy as np
     from oracle import ref
     import workloads
+    # the host's usable cores, at most 16 (the share of the host that one GPU
+    # of the benchmark machine comes with); both numbers are reported
     threads = min(_cores(), 16)
     ref.build()
     ref.set_threads(threads)
@@ -87,12 +95,17 @@ def cpu_baseline(L, N, D, seed, budget_s=12.0):
     dt1 = time.perf_counter() - t1
     ref.set_threads(0)
     return {"value": round(sweeps * L * L / (dt * 1e9), 4), "unit": "attempted site updates/ns",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "host_cores": _cores(), "kind": "oracle",
             "sample": f"first {sweeps} sweeps of the L={L} N={N} D={D} surface from flat, "
                       f"{dt:.1f} s, OpenMP over the tiles of a phase",
             "single_thread": {"value": round(n1 * L1 * L1 / (dt1 * 1e9), 4), "cores": 1,
                               "sample": f"first {n1} sweeps of an L={L1} N={N} D={D} surface "
                                         f"from flat, {dt1:.1f} s"}}
+
+
+def kernel_instance(rocprof_name: str) -> str:
+    from paper_1605_02620_amd import profiling
+    return profiling.kernel_instance(rocprof_name)
 
 
 def _traffic(kname, packed, schedule="checkerboard"):
@@ -104,29 +117,22 @@ def _traffic(kname, packed, schedule="checkerboard"):
     else:
         name = "block_sweep16_traffic.json" if packed else "block_sweep_traffic.json"
     tr = profiling.current_traffic(os.path.join(ROOT, "profiles", name))
-    rk = (tr or {}).get("kernel", "").replace(" ", "")
-    for a, b in ((",unsignedchar,", ",uint8,"), (",signedchar,", ",int8,"), (",short,", ",int16,"),
-                 (",int,", ",int32,")):
-        rk = rk.replace(a, b)
-    # kernel_name() appends ",dt" for the double-tiling instance, whose last
-    # template argument (the schedule) is 1
-    dt = kname.endswith(",dt>")
-    base = kname[:-4] if dt else kname[:-1]
-    if tr is not None and rk.startswith("voidrsosk::" + base + ",") and (",1>(" in rk) == dt:
+    if tr is not None and kernel_instance(tr.get("kernel", "")) == kname:
         return tr["traffic_bytes_per_launch"]
     return None
 
 
-def bench_single(L, N, D, seed, steps, warmup, packed=False, schedule="checkerboard"):
+def bench_single(L, N, D, seed, steps, warmup, packed=False, schedule="checkerboard", tune=True):
     """K sweeps of one surface in one rsos_sweep call (hipGraph replays of
-    the two kernels per sweep), then the same again with every tile-block
-    kernel bracketed by HIP events on the surface's stream (graph replay
-    off) for the dominant kernel's mean duration."""
+    one kernel per sweep), then the same again with every tile-block kernel
+    bracketed by HIP events on the surface's stream (graph replay off) for
+    the dominant kernel's mean duration.  tune: the launch configuration
+    comes from the autotuner (tuned when the surface is created)."""
     import torch
     import paper_1605_02620_amd as rsos
     stream = torch.cuda.Stream()
     s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=max(4096, steps + warmup + 1), stream=stream,
-                     packed=packed, schedule=schedule)
+                     packed=packed, schedule=schedule, tune=tune)
     s.sweep(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -157,52 +163,115 @@ def bench_single(L, N, D, seed, steps, warmup, packed=False, schedule="checkerbo
                 "traffic": _traffic(kname, packed, schedule), "traffic_unit": "bytes per launch",
                 "kernel": kname, "launches_timed": launches, "kernel_mean_ms": round(mean_ms, 4),
                 "algorithmic_bytes_per_launch": L * L * bpa}
+    # the same bytes over the whole timed region (every launch and gap)
+    roofline["frac_end_to_end"] = round(L * L * bpa * steps / dt / 1e9 / HBM_PEAK_GBS, 4)
     moments = {"ms_per_call": round(mom_ms, 4),
                "GBps_read": round(L * L * (bpa // 2) / (mom_ms * 1e-3) / 1e9, 1),
                "phi2": mom["phi2"], "phi3": mom["phi3"], "phi4": mom["phi4"]}
-    return {"value": value, "dt": dt, "w": w, "roofline": roofline, "moments": moments}
+    out = {"value": value, "dt": dt, "w": w, "roofline": roofline, "moments": moments}
+    if tune:
+        from paper_1605_02620_amd import surface
+        out["autotune"] = _tune_summary(surface.tune(L, N, D, packed=packed, schedule=schedule))
+    return out
 
 
-def bench_batched(n_steps_batch=200):
-    """Aggregate attempts/ns: 256-surface ensemble, one launch per sweep for
-    all surfaces, versus one surface per launch (same surfaces, same sweeps)."""
+def _tune_summary(t):
+    return {"shape": f"{t['TX']}x{t['TY']} tiles, {t['NT']} threads, {t['elem']}-byte staging",
+            "xcd_order": {0: "in order", 1: "runs of 16 per XCD", 2: "column strips per XCD"}[t["xmode"]],
+            "graph_sweeps": t["graph_sweeps"], "candidates": t["candidates"],
+            "ms_per_sweep_tuned": round(t["ms_per_sweep"], 4),
+            "ms_per_sweep_first_fit": round(t["ms_first_fit"], 4)}
+
+
+def _run_batch(specs, sweeps, tune, warm=64):
+    import torch
+    import paper_1605_02620_amd as rsos
+    b = rsos.Batch(specs, D=8, log_cap=sweeps + warm + 1, stream=torch.cuda.Stream(), tune=tune)
+    b.sweep(warm)  # also builds the graphs the timed sweeps replay
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(sweeps)
+    w = b.width()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    return dt, w
+
+
+def bench_batched(sweeps=10000, plain_sweeps=1000):
+    """The 256-surface ensemble (L from {256, 512, 1024, 2048}, N = 1):
+    all surfaces swept together for its full 10^4 sweeps, with the
+    autotuner's per-class configurations and with the untuned first-fit
+    one; the plain one-surface-per-launch loop over the same surfaces for
+    plain_sweeps sweeps each (its rate does not depend on the run length
+    once the graphs are built)."""
     import torch
     import paper_1605_02620_amd as rsos
     import workloads
     ens = workloads.cfg_ensemble()
     specs = [(s.L, s.N, s.seed) for s in ens]
     total_sites = sum(L * L for (L, _, _) in specs)
-    # warm-ups of 64 sweeps also build the graphs that the timed sweeps
-    # replay, for both modes
-    warm = 64
-    b = rsos.Batch(specs, D=8, log_cap=4096, stream=torch.cuda.Stream())
-    b.sweep(warm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.sweep(n_steps_batch)
-    b.width()
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    b.close()
+    t_tuned, w_tuned = _run_batch(specs, sweeps, True)
+    t_first, w_first = _run_batch(specs, sweeps, False)
+    assert all(int(a) == int(b) for a, b in zip(w_tuned["s2"], w_first["s2"])), "tuned and first-fit runs differ"
     # plain: every surface its own handle, sweeps issued surface by surface
+    warm = 64
     st = torch.cuda.Stream()
-    surfs = [rsos.Surface(L, N=N, seed=sd, D=8, log_cap=4096, stream=st) for (L, N, sd) in specs]
+    surfs = [rsos.Surface(L, N=N, seed=sd, D=8, log_cap=plain_sweeps + warm + 1, stream=st, tune=True)
+             for (L, N, sd) in specs]
     for s in surfs:
         s.sweep(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in surfs:
-        s.sweep(n_steps_batch)
+        s.sweep(plain_sweeps)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     for s in surfs:
         s.close()
-    rate_b = total_sites * n_steps_batch / (tb * 1e9)
-    rate_p = total_sites * n_steps_batch / (tp * 1e9)
+    rate_b = total_sites * sweeps / (t_tuned * 1e9)
+    rate_f = total_sites * sweeps / (t_first * 1e9)
+    rate_p = total_sites * plain_sweeps / (tp * 1e9)
     return {"workload": "256 surfaces, L from {256,512,1024,2048} (default_rng(20160508)), "
-                        f"N=1, D=8, seeds 0..255, {n_steps_batch} sweeps each",
-            "batched_attempts_per_ns": round(rate_b, 2), "plain_attempts_per_ns": round(rate_p, 2),
-            "batched_over_plain": round(rate_b / rate_p, 3)}
+                        f"N=1, D=8, seeds 0..255, {sweeps} sweeps each (batched); the plain loop "
+                        f"times {plain_sweeps} sweeps per surface",
+            "batched_attempts_per_ns": round(rate_b, 2),
+            "batched_first_fit_attempts_per_ns": round(rate_f, 2),
+            "tuned_over_first_fit": round(rate_b / rate_f, 3),
+            "plain_attempts_per_ns": round(rate_p, 2), "batched_over_plain": round(rate_b / rate_p, 3),
+            "batched_wall_s": round(t_tuned, 3)}
+
+
+def bench_step_heights():
+    """The step-height workload: three 8192^2 surfaces with N = 1, 2, 4,
+    5000 sweeps each, one surface per launch (plain) and the three swept
+    together (batched)."""
+    import torch
+    import paper_1605_02620_amd as rsos
+    import workloads
+    cfg = workloads.cfg_step_heights()
+    n = cfg[0].sweeps
+    sites = sum(c.L * c.L for c in cfg)
+    st = torch.cuda.Stream()
+    surfs = [rsos.Surface(c.L, N=c.N, seed=c.seed, D=c.D, log_cap=n + 65, stream=st, tune=True) for c in cfg]
+    for s in surfs:
+        s.sweep(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in surfs:
+        s.sweep(n)
+    ws = [s.width() for s in surfs]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    for s in surfs:
+        s.close()
+    tb, wb = _run_batch([(c.L, c.N, c.seed) for c in cfg], n, True)
+    assert [int(w["s2"]) for w in ws] == [int(v) for v in wb["s2"]], "plain and batched runs differ"
+    return {"workload": f"3 surfaces L=8192, N=1,2,4, D=8, seed 1, {n} sweeps each",
+            "plain_attempts_per_ns": round(sites * n / (tp * 1e9), 2),
+            "batched_attempts_per_ns": round(sites * n / (tb * 1e9), 2),
+            "plain_wall_s": round(tp, 3),
+            "W2_final": {int(c.N): round(float(w["w2"]), 4) for c, w in zip(cfg, ws)}}
 
 
 def bench_multisurface(L=256, groups=8, sweeps=64):
@@ -258,32 +327,96 @@ def bench_fss(sizes=(32, 64, 128, 256), realizations=256):
             "Q_h": {int(L): round(v["Q_h"], 3) for L, v in r["sizes"].items()}}
 
 
-def bench_served(n_jobs=200, load=0.9, capacity_attempts_per_ns=None, pool_gib=8):
-    """The served workload's job mix (L a power of two in [128, 8192], N in
-    {1, 2, 4}, t_max log-uniform) as a Poisson stream at `load` times the
-    plain path's capacity, through the continuous-batching engine.
-    t_max is drawn from [100, 2000] (the full workload's [100, 20000] with
-    2000 jobs runs for minutes) so the default run stays short."""
+def served_jobs(n_jobs):
+    """The first n_jobs jobs of the served stream (2000 jobs, default_rng(5):
+    L = 2^7..2^13, N in {1, 2, 4}, t_max log-uniform in [100, 20000])."""
+    import workloads
+    return workloads.job_stream(n_jobs=2000, rate_per_s=1.0, seed=5)[:n_jobs]
+
+
+def bench_plain_jobs(jobs):
+    """The plain one-surface-per-launch loop over a job set: each job alone,
+    one after the other, on one stream; aggregate attempted updates/ns."""
+    import torch
+    import paper_1605_02620_amd as rsos
+    import workloads
+    st = torch.cuda.Stream()
+    attempts = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in jobs:
+        s = rsos.Surface(j.L, N=j.N, seed=j.seed, D=8, log_cap=j.t_max + 1, stream=st, tune=True)
+        s.sweep(j.t_max)
+        s.log(1, j.t_max)  # the job's records (synchronises)
+        s.close()
+        attempts += j.L * j.L * j.t_max
+    dt = time.perf_counter() - t0
+    return attempts / (dt * 1e9), dt
+
+
+def bench_served(jobs, rate_attempts_per_ns=None, load=0.9, pool_gib=8, tune=True):
+    """The jobs through the continuous-batching engine: as a Poisson stream
+    at `load` times the given rate (attempted updates per ns), or all
+    arriving at once (rate None: the engine's capacity on this job set);
+    p50/p99 latency from arrival and aggregate attempted updates/ns."""
     import numpy as np
     import torch
     from paper_1605_02620_amd import serve
     import workloads
-    probe = workloads.job_stream(n_jobs=n_jobs, rate_per_s=1.0, seed=5, t_range=(100, 2000))
-    mean_attempts = float(np.mean([j.L * j.L * j.t_max for j in probe]))
-    cap = capacity_attempts_per_ns or 400.0
-    rate = load * cap * 1e9 / mean_attempts  # jobs per second
-    jobs = workloads.job_stream(n_jobs=n_jobs, rate_per_s=rate, seed=5, t_range=(100, 2000))
-    eng = serve.Engine(pool_bytes=pool_gib << 30, max_running=256, D=8)
-    res, summ = serve.serve(eng, jobs, grid=lambda tm: workloads.pow2_grid(tm))
+    if rate_attempts_per_ns is None:
+        arr = np.zeros(len(jobs))
+        rate = None
+    else:
+        mean_attempts = float(np.mean([j.L * j.L * j.t_max for j in jobs]))
+        rate = load * rate_attempts_per_ns * 1e9 / mean_attempts  # jobs per second
+        rng = np.random.default_rng(55)
+        gaps = rng.exponential(1.0 / rate, size=len(jobs))
+        arr = np.cumsum(gaps) - gaps[0]
+    timed = [workloads.Job(job_id=j.job_id, arrival_s=float(a), L=j.L, N=j.N, t_max=j.t_max, seed=j.seed)
+             for j, a in zip(jobs, arr)]
+    eng = serve.Engine(pool_bytes=pool_gib << 30, max_running=256, D=8, tune=tune)
+    res, summ = serve.serve(eng, timed, grid=lambda tm: workloads.pow2_grid(tm))
     eng.close()
     torch.cuda.synchronize()
-    return {"workload": f"{n_jobs} jobs, Poisson arrivals at {rate:.2f}/s ({load} x the plain "
-                        f"capacity {cap:.0f} attempts/ns), L = 2^7..2^13, N in {{1,2,4}}, "
-                        f"t_max log-uniform in [100, 2000], {pool_gib} GiB pool",
-            "jobs_done": summ["jobs_done"], "wall_s": round(summ["wall_s"], 3),
-            "attempts_per_ns": round(summ["attempts_per_ns"], 2),
-            "latency_p50_s": round(summ["latency_p50_s"], 4),
-            "latency_p99_s": round(summ["latency_p99_s"], 4)}
+    out = {"jobs_done": summ["jobs_done"], "wall_s": round(summ["wall_s"], 3),
+           "attempts_per_ns": round(summ["attempts_per_ns"], 2),
+           "latency_p50_s": round(summ["latency_p50_s"], 4),
+           "latency_p99_s": round(summ["latency_p99_s"], 4)}
+    if rate is not None:
+        out["arrival_rate_per_s"] = round(rate, 3)
+    return out
+
+
+def bench_serving(n_jobs):
+    """Served against plain on the same jobs.  The autotuner's choices for
+    every (L, N) class of the job set are made first (setup, outside every
+    timed region).  capacity: all jobs arrive at once; then Poisson streams
+    at 0.9 and 0.5 of that capacity (latency from arrival), and at 0.9 with
+    the untuned first-fit launch choice."""
+    from paper_1605_02620_amd import surface
+    jobs = served_jobs(n_jobs)
+    for (L, N) in sorted({(j.L, j.N) for j in jobs}):
+        if L * L * 4 > 64 * 1024:
+            surface.tune(L, N, 8, batch=True)
+            surface.tune(L, N, 8)
+    plain_rate, plain_s = bench_plain_jobs(jobs)
+    _progress(f"served: plain loop {plain_rate:.1f} attempts/ns")
+    full = n_jobs >= 2000
+    out = {"workload": (f"{'all' if full else 'the first'} {n_jobs} jobs of the served stream (2000 jobs, "
+                        "default_rng(5): L = 2^7..2^13, N in {1,2,4}, t_max log-uniform in [100, 20000]), "
+                        "8 GiB pool" + ("" if full else "; reduced from the full 2000-job stream to keep the "
+                                                        "default run short")),
+           "attempts": int(sum(j.L * j.L * j.t_max for j in jobs)),
+           "plain_attempts_per_ns": round(plain_rate, 2), "plain_wall_s": round(plain_s, 3)}
+    cap = bench_served(jobs)
+    out["capacity"] = cap
+    out["served_over_plain"] = round(cap["attempts_per_ns"] / plain_rate, 3)
+    _progress(f"served: capacity {cap['attempts_per_ns']} attempts/ns")
+    out["at_0.9_load"] = bench_served(jobs, cap["attempts_per_ns"], 0.9)
+    _progress("served: 0.9 load done")
+    out["at_0.9_load_first_fit"] = bench_served(jobs, cap["attempts_per_ns"], 0.9, tune=False)
+    out["at_0.5_load"] = bench_served(jobs, cap["attempts_per_ns"], 0.5)
+    return out
 
 
 def main():
@@ -304,6 +437,13 @@ def main():
                     help="tile schedule of the headline surface (the double-tiling leg uses 'double')")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (calibrates HBM counters)")
+    ap.add_argument("--no-step", action="store_true", help="skip the step-height leg")
+    ap.add_argument("--served-jobs", type=int, default=200,
+                    help="jobs of the 2000-job served stream to serve (2000: the whole stream)")
+    ap.add_argument("--no-tune", action="store_true", help="headline without the autotuner")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: read before the run if it exists, written after the "
+                         "headline (profiling runs reuse the choices without timing candidates)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -315,9 +455,16 @@ def main():
 
     cfg = workloads.cfg_single()
     L, N, D, seed = cfg.L, cfg.N, cfg.D, cfg.seed
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        from paper_1605_02620_amd import surface
+        surface.tune_load(args.tune_cache)
     head = bench_single(L, N, D, seed, args.steps, args.warmup, packed=args.storage == "packed16",
-                        schedule=args.schedule)
+                        schedule=args.schedule, tune=not args.no_tune)
     value, dt, w, roofline = head["value"], head["dt"], head["w"], head["roofline"]
+    if args.tune_cache:
+        from paper_1605_02620_amd import surface
+        surface.tune_save(args.tune_cache)
+    _progress(f"headline: {value:.1f} attempts/ns")
     out = {"metric": "attempted site updates/ns", "value": round(value, 3),
            "unit": "attempts/ns", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
@@ -329,6 +476,8 @@ def main():
                       "storage": args.storage, "schedule": args.schedule,
                       "final_t": int(w["t"]), "final_w2": float(w["w2"])},
            "roofline": roofline, "moments": head["moments"]}
+    if "autotune" in head:
+        out["autotune"] = head["autotune"]
     if args.storage == "int32" and args.schedule == "checkerboard" and not args.no_packed:
         # the same surface and sweeps with heights kept as 16-bit residues
         # (identical results; 4 B per attempt)
@@ -351,6 +500,10 @@ def main():
         del src, dst
     if not args.no_batch:
         out["batched"] = bench_batched()
+        _progress(f"batched: {out['batched']['batched_attempts_per_ns']} attempts/ns")
+    if not args.no_step:
+        out["step_heights"] = bench_step_heights()
+        _progress("step heights done")
     if not args.no_dt:
         # the paper's double-tiling schedule on the same surface (a different
         # but equally valid dynamics; same 8 B per attempt)
@@ -361,18 +514,16 @@ def main():
                                 "roofline": dtr["roofline"]}
     if not args.no_ms:
         out["multisurface"] = bench_multisurface()
+        _progress("multisurface done")
     if not args.no_fss:
         out["steady_state"] = bench_fss()
+        _progress("steady state done")
     if not args.no_serve:
-        # capacity of the plain path: one surface per launch at the rate the
-        # single large surface reaches (the job mix's attempts are dominated
-        # by its largest lattices)
-        out["served"] = bench_served(capacity_attempts_per_ns=value)
-        half = bench_served(load=0.5, capacity_attempts_per_ns=value)
-        out["served"]["at_half_load"] = {k: half[k] for k in ("jobs_done", "wall_s", "attempts_per_ns",
-                                                              "latency_p50_s", "latency_p99_s")}
+        out["served"] = bench_serving(args.served_jobs)
+        _progress("served done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, N, D, seed)
+        _progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

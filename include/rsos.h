@@ -67,7 +67,9 @@ typedef enum {
  *         (the paper uses 8 x 8 domains, Sec. II, and tests 16 x 16,
  *         Sec. III.C); part of the result;
  *   flags 0, RSOS_FLAG_PACKED16 (storage only: results are identical) or
- *         RSOS_FLAG_DT4 (the double-tiling schedule);
+ *         RSOS_FLAG_DT4 (the double-tiling schedule), optionally or-ed with
+ *         RSOS_FLAG_TUNE (launch choices from the autotuner; results are
+ *         identical);
  *   seed  64-bit Philox key. */
 typedef struct {
     int32_t L;
@@ -99,6 +101,11 @@ typedef struct {
  * schedule.  D must be 8 or 16; int32 storage only (not combined with
  * RSOS_FLAG_PACKED16); single surfaces and batches. */
 #define RSOS_FLAG_DT4 2
+
+/* Launch choices from the autotuner (see rsos_tune below) instead of the
+ * first tile-block variant that fits.  Changes speed only, never results.
+ * The environment variable RSOS_TUNE=1 sets it for every handle. */
+#define RSOS_FLAG_TUNE 4
 
 /* One record of the per-sweep log: the state after t sweeps.
  *   s1 = sum h, s2 = sum h^2 (exact), accepted = accepted attempts of sweep
@@ -157,12 +164,18 @@ typedef struct rsos_engine rsos_engine;
 rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, int32_t *d_work,
                       const int32_t *h0_host, int64_t t0, int64_t log_cap, void *stream);
 
-/* Enqueues n_mcs sweeps (asynchronous on the surface's stream); t += n_mcs.
- * Checks the overflow bound max(h0) + min(t + N L, D^2 t) < 2^31 and
- * L^2 H^2 < 2^63 before enqueuing (RSOS_E_OVERFLOW). */
+/* Enqueues n_mcs Monte-Carlo sweeps (Sec. II: one sweep = L*L attempted
+ * depositions, here D*D per tile of each checkerboard colour) asynchronously
+ * on the surface's stream; t += n_mcs.  n_mcs = 0 does nothing; n_mcs < 0
+ * or t + n_mcs > 2^32 gives RSOS_E_INVAL.  Checks the overflow bound
+ * H = max(h0) + min(t + N L, D^2 t) < 2^31 and L^2 H^2 < 2^63 before
+ * enqueuing anything (RSOS_E_OVERFLOW: no device work, t unchanged).  Each
+ * sweep is one kernel launch (runs of them replayed as hipGraphs when the
+ * surface has a stream); the exact sums of the sweep are part of it. */
 rsos_status rsos_sweep(rsos_surface *s, int64_t n_mcs);
 
-/* Synchronises the stream and returns the record of the current time t. */
+/* Synchronises the stream and returns the record of the current time t:
+ * S1, S2, the accepted count and W^2(L, t) of Eq. (2). */
 rsos_status rsos_width(rsos_surface *s, rsos_width_t *out);
 
 /* Synchronises and returns records t_from .. t_from+n-1 (t_from >= t0).
@@ -191,10 +204,14 @@ rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current);
 rsos_status rsos_timing(rsos_surface *s, int enable);
 rsos_status rsos_timing_read(rsos_surface *s, int64_t *launches, double *mean_ms, double *total_ms);
 
-/* Name of the tile-block kernel instance that sweeps this surface, e.g.
- * "block_sweep<8,16,8,128,int16>" (D, tiles per block in x and y, threads,
- * LDS element type), or "lds_run<8>" for an LDS-resident surface; written
- * NUL-terminated into buf (at most len bytes). */
+/* Name of the tile-block kernel instance that sweeps this surface, in the
+ * form rocprofv3 shows its template arguments: e.g.
+ * "block_sweep<8,32,8,256,int8,int16,0>" (D, tiles per block in x and y,
+ * threads, LDS element type, the wider type of blocks that do not fit it,
+ * schedule), "block_sweep16<8,32,8,256,0>" with 16-bit storage, or
+ * "lds_run<8,256,0>" for an LDS-resident surface; written NUL-terminated
+ * into buf (at most len bytes).  With several kernel instances (a tuned
+ * batch) the first one. */
 rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len);
 
 /* Frees the handle and library-owned memory (never d_h, never a
@@ -250,7 +267,10 @@ rsos_status rsos_ms_free(rsos_ms *m);
 /* one launch per sweep.  Independent realization sets, Sec. II.          */
 /* --------------------------------------------------------------------- */
 
-/* n surfaces; p[i] their parameters (all with the same D and flags);
+/* n surfaces; p[i] their parameters (all with the same D and flags; with
+ * RSOS_FLAG_TUNE each (L, N) class gets the autotuner's batched choice, and
+ * surfaces with different choices are swept by separate kernel instances
+ * in the same sweep);
  * d_pool / d_work_pool caller-owned device int32 pools, surface i at
  * element offsets[i] of each (L_i^2 elements, offsets[] host array);
  * d_work_pool NULL makes the library allocate the second pool.  Flat start,
@@ -335,7 +355,83 @@ rsos_status rsos_engine_release(rsos_engine *e, int64_t job_id);
  * [4] ticks, [5] attempted site updates so far. */
 rsos_status rsos_engine_stats(rsos_engine *e, int64_t out[6]);
 
+/* Launch choice of the engine's tile-block jobs: with enable != 0 each
+ * chunk sweeps the running jobs with the autotuner's batched choice for the
+ * (L, N) class that holds the most sites among them, when that variant fits
+ * every running job (a class is tuned on first use, between chunks; load a
+ * saved cache with rsos_tune_load to avoid that); otherwise, and with
+ * enable = 0 (the default), with the first variant that fits them all.
+ * Results never change. */
+rsos_status rsos_engine_tune(rsos_engine *e, int32_t enable);
+
 rsos_status rsos_engine_destroy(rsos_engine *e);
+
+/* --------------------------------------------------------------------- */
+/* Autotuner.  The paper chooses its tile layout for the GPU it runs on    */
+/* (Sec. II; domain sizes compared in Sec. III.C).  Here the domain size D */
+/* is part of the result and is never tuned; the autotuner picks, per key  */
+/* (device, D, L, N, storage and schedule flags, alone or batched), the    */
+/* launch knobs that leave every result unchanged: the tile-block variant  */
+/* (block shape, threads per workgroup, LDS staging type), the order in    */
+/* which workgroups take blocks across the 8 XCDs, and the sweeps per      */
+/* captured hipGraph.  It times every candidate with HIP events on a       */
+/* scratch workload of the key (flat surfaces; one surface when alone,     */
+/* ceil(2^24 / L^2) surfaces in one launch when batched; L > 16384 tuned   */
+/* on a 16384^2 stand-in) and caches the fastest for the process.  Tuning */
+/* allocates scratch device memory (two int32 pools of the workload) and   */
+/* synchronises; it never touches a caller's surface.  The cache is        */
+/* process-wide and guarded by a mutex.                                    */
+/* --------------------------------------------------------------------- */
+
+/* One launch configuration.
+ *   TX, TY, NT    tiles per block in x and y, threads per workgroup;
+ *   elem          LDS bytes per staged site (1: int8, with int16
+ *                 sub-blocks where a block's range does not fit; 2; 4);
+ *   xmode         workgroup -> block order: 0 in order, 1 runs of 16
+ *                 blocks per XCD, 2 one column strip of blocks per XCD
+ *                 (single surfaces whose block columns divide by 8);
+ *   graph_sweeps  sweeps per captured hipGraph;
+ *   candidates    configurations timed for the key;
+ *   measured      1 if chosen by timing on this process's device, 0 if
+ *                 entered by rsos_tune_set (or loaded as such);
+ *   ms_per_sweep  the chosen configuration's mean sweep time on the
+ *                 tuning workload (0 if not measured);
+ *   ms_first_fit  the untuned default's (first fitting variant, xmode 1)
+ *                 on the same workload. */
+typedef struct {
+    int32_t TX, TY, NT, elem;
+    int32_t xmode;
+    int32_t graph_sweeps;
+    int32_t candidates;
+    int32_t measured;
+    double ms_per_sweep;
+    double ms_first_fit;
+} rsos_tune_t;
+
+/* The cached configuration of p's key (batch != 0: tuned for surfaces
+ * swept together with others), tuning it now if there is none.  L must be
+ * on the tile-block path (L^2 * 4 > 64 KiB; RSOS_E_INVAL otherwise). */
+rsos_status rsos_tune(const rsos_params *p, int32_t batch, rsos_tune_t *out);
+
+/* Lists the candidates of p's key: *n receives their number, the first
+ * min(*n, cap) are written to out (shape fields; and, if the key has been
+ * tuned in this process, measured = 1 and the candidate's own time in
+ * ms_per_sweep). */
+rsos_status rsos_tune_candidates(const rsos_params *p, int32_t batch, rsos_tune_t *out, int32_t cap, int32_t *n);
+
+/* Enters a configuration for p's key without timing (it must fit the key:
+ * RSOS_E_INVAL otherwise); later handles created with RSOS_FLAG_TUNE use
+ * it.  Meant for tests and for reusing results of another process. */
+rsos_status rsos_tune_set(const rsos_params *p, int32_t batch, const rsos_tune_t *choice);
+
+/* Empties the cache. */
+rsos_status rsos_tune_clear(void);
+
+/* Writes the cache as text, one line per key; reads such a file back into
+ * the cache (lines whose configuration no longer exists or fits are
+ * skipped).  RSOS_E_INVAL if the file cannot be written or read. */
+rsos_status rsos_tune_save(const char *path);
+rsos_status rsos_tune_load(const char *path);
 
 /* --------------------------------------------------------------------- */
 /* Utilities.                                                             */
@@ -353,6 +449,13 @@ const char *rsos_last_error(void);
 
 /* Library version string. */
 const char *rsos_version(void);
+
+/* For tests of the error paths, on the calling thread: the after-th HIP
+ * runtime call the library makes from now on is not made and reports a
+ * runtime error instead (RSOS_E_DEVICE, and the handle it belongs to is
+ * failed for good, exactly as after a real one); 0 turns this off.  No
+ * device work is involved. */
+rsos_status rsos_debug_fail(int32_t after);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,7 @@ OK, E_INVAL, E_RSOS, E_OVERFLOW, E_DEVICE, E_NOMEM, E_STATE, E_BUSY = 0, -1, -2,
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 FLAG_PACKED16 = 1
 FLAG_DT4 = 2
+FLAG_TUNE = 4
 
 
 class Params(ctypes.Structure):
@@ -46,6 +47,15 @@ class Moments(ctypes.Structure):
             return v - (1 << 128) if v >> 127 else v
         return {"t": self.t, "ref": self.ref, "c1": self.c1, "c2": self.c2, "c3": i128(self.c3),
                 "c4": i128(self.c4), "phi2": self.phi2, "phi3": self.phi3, "phi4": self.phi4}
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("TX", c_i32), ("TY", c_i32), ("NT", c_i32), ("elem", c_i32), ("xmode", c_i32),
+                ("graph_sweeps", c_i32), ("candidates", c_i32), ("measured", c_i32),
+                ("ms_per_sweep", ctypes.c_double), ("ms_first_fit", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class RsosError(RuntimeError):
@@ -88,12 +98,20 @@ SIGNATURES = [
     ("rsos_engine_cancel", c_i32, [c_vp, c_i64]),
     ("rsos_engine_release", c_i32, [c_vp, c_i64]),
     ("rsos_engine_stats", c_i32, [c_vp, P(c_i64)]),
+    ("rsos_engine_tune", c_i32, [c_vp, c_i32]),
     ("rsos_engine_destroy", c_i32, [c_vp]),
+    ("rsos_tune", c_i32, [P(Params), c_i32, P(Tune)]),
+    ("rsos_tune_candidates", c_i32, [P(Params), c_i32, P(Tune), c_i32, P(c_i32)]),
+    ("rsos_tune_set", c_i32, [P(Params), c_i32, P(Tune)]),
+    ("rsos_tune_clear", c_i32, []),
+    ("rsos_tune_save", c_i32, [ctypes.c_char_p]),
+    ("rsos_tune_load", c_i32, [ctypes.c_char_p]),
     ("rsos_philox4x32_10", None, [P(c_u32), P(c_u32), P(c_u32)]),
     ("rsos_w2", ctypes.c_double, [c_i32, c_i64, c_i64]),
     ("rsos_strerror", ctypes.c_char_p, [c_i32]),
     ("rsos_last_error", ctypes.c_char_p, []),
     ("rsos_version", ctypes.c_char_p, []),
+    ("rsos_debug_fail", c_i32, [c_i32]),
 ]
 
 _lib = None

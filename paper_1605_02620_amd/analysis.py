@@ -9,7 +9,7 @@ host over results the GPU path has produced (W^2 records, moment records).
                          of sample averages of Phi_3, Phi_4 and Phi_2
   effective_exponent     local slopes of Eq. (8) between consecutive sizes
                          (or times), at the midpoints of the pairs
-  power_fit              slope of ln y against ln x (direct fit of Eq. (9))
+  power_fit              slope of ln y against ln x (direct fit of Eq. (12))
   stderr                 sigma / sqrt(n - 1) over independent realizations
 """
 from __future__ import annotations

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "rsos.hip")
-HDRS = [os.path.join(PKG, "csrc", f) for f in ("rsos_kernels.hpp", "rsos_moments.hpp", "rsos_ms.hpp", "rsos_engine.inc", "rsos_ms.inc")] + [
+HDRS = [os.path.join(PKG, "csrc", f) for f in ("rsos_kernels.hpp", "rsos_host.hpp", "rsos_moments.hpp", "rsos_ms.hpp", "rsos_engine.inc", "rsos_ms.inc", "rsos_tune.inc")] + [
     os.path.join(ROOT, "include", "rsos.h")]
 OUT = os.path.join(PKG, "librsos.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,11 +1,12 @@
 // rsos.hip -- host runtime and C ABI of librsos.so (see include/rsos.h).
 //
-// Launch plan per sweep: block_sweep over every tile block of every active
-// surface, then reduce_acc (one workgroup per surface).  Both kernels
-// read the surface time t from device memory, so a captured hipGraph of K
-// sweeps replays for any t.  Surfaces whose L^2 int32 fit in LDS run all
+// Launch plan per sweep: one block_sweep launch over every tile block of
+// every active surface (the last block of each surface also folds its
+// exact sums into the per-sweep log).  The kernel reads the surface time t
+// from device memory, so a captured hipGraph of K sweeps replays for any t.  Surfaces whose L^2 int32 fit in LDS run all
 // their sweeps in one lds_run launch instead.
 #include "rsos.h"
+#include "rsos_host.hpp"
 #include "rsos_kernels.hpp"
 #include "rsos_moments.hpp"
 #include "rsos_ms.hpp"
@@ -23,117 +24,97 @@
 #include <vector>
 
 using rsosk::SurfDev;
+using rsosh::check_overflow;
+using rsosh::fail;
+using rsosh::g_last_error;
+using rsosh::validate_h0;
+using rsosh::w2_of;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-rsos_status fail(rsos_status st, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return st;
-}
-
+// Every HIP runtime call of the library goes through HIP_TRY.  A test can
+// make the n-th next one on its thread report a failure (rsos_debug_fail)
+// to exercise the error paths without a real device error.
 #define HIP_TRY(expr)                                                                       \
     do {                                                                                    \
+        if (rsosh::g_fail_countdown > 0 && --rsosh::g_fail_countdown == 0)                  \
+            return fail(RSOS_E_DEVICE, "%s: failure injected by rsos_debug_fail", #expr);   \
         hipError_t e_ = (expr);                                                             \
         if (e_ != hipSuccess) return fail(RSOS_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
 constexpr int kLdsMaxBytes = 64 * 1024;  // lds_run: whole surface in LDS
 constexpr int kGraphSweeps = 32;
-constexpr int kFallbackGrid = 256;  // workgroups walking the fallback queue
+constexpr long long kNoEnd = 0x7FFFFFFFFFFFFFFFll;  // t_end of a surface with no bound
 constexpr int kPsGrid = 2048;       // workgroups of the power-sum reduction
 
 // ---------------------------------------------------------------------------
 // Block-kernel variants.  The tile block shape never changes results; it
 // only has to tile the lattice: T % TX == 0, T % TY == 0, region <= L.
 // ---------------------------------------------------------------------------
-typedef void (*BlockLaunch)(dim3, hipStream_t, const SurfDev *, int, const int *, int *);
+typedef void (*BlockLaunch)(dim3, hipStream_t, SurfDev *, int, const int *, int, int);
 
-template <int D, int TX, int TY, int NT, typename E, bool FB>
-void launch_block(dim3 grid, hipStream_t st, const SurfDev *d, int n, const int *owner, int *queue)
+// E: LDS element type; EW: wider type for the blocks whose range does not
+// fit E (void: E always fits); SCHED 1: the double-tiling schedule
+template <int D, int TX, int TY, int NT, typename E, typename EW, int SCHED>
+void launch_block(dim3 grid, hipStream_t st, SurfDev *d, int n, const int *owner, int xmode, int xnbx)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, owner, queue);
+    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, EW, SCHED>), grid, dim3(NT), 0, st, d, n, owner,
+                       xmode, xnbx);
 }
 
-template <int D, int TX, int TY, int NT, typename E, bool FB>
-void launch_block16(dim3 grid, hipStream_t st, const SurfDev *d, int n, const int *owner, int *queue)
+template <int D, int TX, int TY, int NT>
+void launch_block16(dim3 grid, hipStream_t st, SurfDev *d, int n, const int *owner, int xmode, int xnbx)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT, E, FB>), grid, dim3(NT), 0, st, d, n, owner, queue);
-}
-
-template <int D, int TX, int TY, int NT, typename E, bool FB>
-void launch_block_dt(dim3 grid, hipStream_t st, const SurfDev *d, int n, const int *owner, int *queue)
-{
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, FB, 1>), grid, dim3(NT), 0, st, d, n, owner, queue);
+    hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT>), grid, dim3(NT), 0, st, d, n, owner, xmode, xnbx);
 }
 
 // The double-tiling schedule is built for the domain sizes the paper
 // compares (8 and 16) on int32 storage.
-template <int D, int TX, int TY, int NT, typename E, bool FB>
+template <int D, int TX, int TY, int NT, typename E, typename EW>
 constexpr BlockLaunch dt_launcher()
 {
-    if constexpr (D == 8 || D == 16) return launch_block_dt<D, TX, TY, NT, E, FB>;
+    if constexpr (D == 8 || D == 16) return launch_block<D, TX, TY, NT, E, EW, 1>;
     else return nullptr;
 }
 
 struct Variant {
     int D, TX, TY, NT, elem;  // elem: LDS bytes per site (1 and 2: offsets from a block reference)
-    BlockLaunch launch;
-    BlockLaunch fallback;     // for elem == 1: the same blocks with wider staging
-    int fb_elem;
-    // 16-bit storage: uint8 staging with an int16 fallback (nullptr: the
-    // shape is not offered for 16-bit storage)
-    BlockLaunch launch16;
-    BlockLaunch fallback16;
-    // double-tiling schedule (int32 storage; nullptr where not offered)
-    BlockLaunch launch_dt;
-    BlockLaunch fallback_dt;
+    BlockLaunch launch;       // int32 storage (elem 1: int16 sub-blocks where int8 does not fit)
+    BlockLaunch launch16;     // 16-bit storage, uint8 staging with int16 sub-blocks (nullptr: not offered)
+    BlockLaunch launch_dt;    // double-tiling schedule, int32 storage (nullptr: not offered)
 };
 
-// int8 staging checks every block's range and queues the few that do not
-// fit for a second launch of the same block shape with int16 (or int32)
-// staging.
-#define P16(D, TX, TY, NT) \
-    launch_block16<D, TX, TY, NT, uint8_t, false>, launch_block16<D, TX, TY, NT, int16_t, true>
-#define DT(D, TX, TY, NT, E, FE) \
-    dt_launcher<D, TX, TY, NT, E, false>(), dt_launcher<D, TX, TY, NT, FE, true>()
-#define DT1(D, TX, TY, NT, E) dt_launcher<D, TX, TY, NT, E, false>(), nullptr
+#define P16(D, TX, TY, NT) launch_block16<D, TX, TY, NT>
 #define V8(D, TX, TY, NT)                                                                     \
-    {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
-     launch_block<D, TX, TY, NT, int16_t, true>, 2, P16(D, TX, TY, NT), DT(D, TX, TY, NT, int8_t, int16_t)}
-#define V8W(D, TX, TY, NT)                                                                    \
-    {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, false>,                             \
-     launch_block<D, TX, TY, NT, int32_t, true>, 4, nullptr, nullptr, DT(D, TX, TY, NT, int8_t, int32_t)}
+    {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, int16_t, 0>, P16(D, TX, TY, NT),    \
+     dt_launcher<D, TX, TY, NT, int8_t, int16_t>()}
+#define V8N(D, TX, TY, NT)                                                                     \
+    {D, TX, TY, NT, 1, launch_block<D, TX, TY, NT, int8_t, int16_t, 0>, nullptr,                \
+     dt_launcher<D, TX, TY, NT, int8_t, int16_t>()}
 #define V16(D, TX, TY, NT) \
-    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, nullptr, nullptr, \
-     DT1(D, TX, TY, NT, int16_t)}
+    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, void, 0>, nullptr, dt_launcher<D, TX, TY, NT, int16_t, void>()}
 #define V16P(D, TX, TY, NT) \
-    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, false>, nullptr, 0, P16(D, TX, TY, NT), \
-     DT1(D, TX, TY, NT, int16_t)}
+    {D, TX, TY, NT, 2, launch_block<D, TX, TY, NT, int16_t, void, 0>, P16(D, TX, TY, NT), \
+     dt_launcher<D, TX, TY, NT, int16_t, void>()}
 #define V32(D, TX, TY, NT) \
-    {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, false>, nullptr, 0, nullptr, nullptr, \
-     DT1(D, TX, TY, NT, int32_t)}
-// In order of preference; the first one that fits every surface is used.
+    {D, TX, TY, NT, 4, launch_block<D, TX, TY, NT, int32_t, void, 0>, nullptr, dt_launcher<D, TX, TY, NT, int32_t, void>()}
+// In order of preference; without a tuned choice the first one that fits
+// every surface is used.
+// (V8N: the same int8 kernel without a 16-bit storage instance, where a
+// V16P entry of the same shape already provides it.)  The autotuner times
+// every entry that fits.
 const Variant kVariants[] = {
-    V16P(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64),
-    V16P(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64),
-    V8(8, 32, 8, 256), V8W(8, 32, 8, 256), V16P(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
-    V32(8, 8, 8, 64), V32(8, 2, 2, 64),
-    V16P(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64),
+    V16P(2, 32, 32, 256), V32(2, 16, 16, 128), V32(2, 2, 2, 64), V8(2, 64, 32, 256),
+    V16P(4, 16, 16, 128), V32(4, 16, 16, 128), V32(4, 2, 2, 64), V8(4, 32, 16, 256),
+    V8(8, 32, 8, 256), V16P(8, 16, 8, 128), V16(8, 8, 8, 64), V32(8, 16, 8, 128),
+    V32(8, 8, 8, 64), V32(8, 2, 2, 64), V8(8, 16, 16, 256), V8N(8, 16, 8, 128),
+    V16P(16, 4, 4, 64), V32(16, 4, 4, 64), V32(16, 2, 2, 64), V8(16, 4, 4, 64), V8(16, 8, 8, 256),
     V8(32, 2, 2, 64), V32(32, 2, 2, 64),
 };
 #undef P16
-#undef DT
-#undef DT1
 #undef V8
-#undef V8W
+#undef V8N
 #undef V16
 #undef V16P
 #undef V32
@@ -150,13 +131,14 @@ bool variant_fits(const Variant &v, int L, int N, bool packed, bool dt = false)
     // from the same inputs)
     if (rwl > L && !(v.TX * v.D == L && rwl <= 2 * L)) return false;
     // int16 staging: every staged value within 32767 of the block reference
+    // (the int16 sub-blocks of a block that int8 staging does not fit are
+    // smaller than the block, so the block's bound covers them)
     const bool i16_ok = (long long)N * (rw + rh + 4) + v.D * v.D <= 32767;
-    // 16-bit storage: uint8 staging (N D <= 96) and the int16 fallback
+    // 16-bit storage: uint8 staging (N D <= 96) and the int16 sub-blocks
     if (packed) return v.launch16 && L % 8 == 0 && (long long)N * v.D <= 96 && i16_ok;
     if (v.elem == 2 && !i16_ok) return false;
-    // int8 staging: the sweep's growth N D must leave room in the byte; the
-    // fallback's wider type must hold the blocks that still do not fit
-    if (v.elem == 1 && ((long long)N * v.D > 96 || (v.fb_elem == 2 && !i16_ok))) return false;
+    // int8 staging: the sweep's growth N D must leave room in the byte
+    if (v.elem == 1 && ((long long)N * v.D > 96 || !i16_ok)) return false;
     return true;
 }
 
@@ -231,7 +213,7 @@ rsos_status check_params(const rsos_params *p)
     if (p->L < 2 * p->D || p->L > 65536 || p->L % (2 * p->D) != 0)
         return fail(RSOS_E_INVAL, "L=%d: must be a multiple of 2D=%d in [2D, 65536]", p->L, 2 * p->D);
     if (p->N < 1) return fail(RSOS_E_INVAL, "N=%d: must be >= 1", p->N);
-    if (p->flags & ~(RSOS_FLAG_PACKED16 | RSOS_FLAG_DT4))
+    if (p->flags & ~(RSOS_FLAG_PACKED16 | RSOS_FLAG_DT4 | RSOS_FLAG_TUNE))
         return fail(RSOS_E_INVAL, "unknown flags 0x%x", (unsigned)p->flags);
     if (p->flags & RSOS_FLAG_DT4) {
         if (p->flags & RSOS_FLAG_PACKED16)
@@ -245,48 +227,6 @@ rsos_status check_params(const rsos_params *p)
 }
 
 bool uses_lds(int L) { return (long long)L * L * 4 <= kLdsMaxBytes; }
-
-// H bounds every height after dt more sweeps: the mean grows at most one
-// per sweep and the restriction keeps the spread on the torus <= N L; also
-// no site gets more than D^2 deposits per sweep.
-rsos_status check_overflow(const rsos_params &p, long long max_h0, long long dt)
-{
-    const __int128 a = (__int128)dt + (__int128)p.N * p.L;
-    const __int128 b = (__int128)dt * p.D * p.D;
-    const __int128 H = (__int128)max_h0 + (a < b ? a : b);
-    if (H >= ((__int128)1 << 31) - 1) return fail(RSOS_E_OVERFLOW, "heights could reach 2^31");
-    const __int128 LH = (__int128)p.L * H;
-    if (LH * LH >= ((__int128)1 << 63)) return fail(RSOS_E_OVERFLOW, "sum h^2 could reach 2^63");
-    return RSOS_OK;
-}
-
-double w2_of(int L, long long s1, long long s2)
-{
-    const __int128 L2 = (__int128)L * L;
-    const __int128 num = L2 * s2 - (__int128)s1 * s1;
-    return (double)num / ((double)L2 * (double)L2);
-}
-
-rsos_status validate_h0(const int32_t *h, int L, int N, long long *max_h, long long *s1, long long *s2)
-{
-    long long mx = 0, a = 0, b = 0;
-    for (int y = 0; y < L; ++y)
-        for (int x = 0; x < L; ++x) {
-            const long long c = h[(size_t)y * L + x];
-            if (c < 0 || c >= (1ll << 30)) return fail(RSOS_E_INVAL, "h0 outside [0, 2^30)");
-            const long long r = h[(size_t)y * L + (x + 1) % L];
-            const long long u = h[(size_t)((y + 1) % L) * L + x];
-            if (llabs(c - r) > N || llabs(c - u) > N)
-                return fail(RSOS_E_RSOS, "h0 violates |dh| <= %d at (%d, %d)", N, x, y);
-            mx = std::max(mx, c);
-            a += c;
-            b += c * c;
-        }
-    *max_h = mx;
-    *s1 = a;
-    *s2 = b;
-    return RSOS_OK;
-}
 
 // Pinned staging for small host->device descriptor updates; the event makes
 // sure the previous copy is done before the buffer is rewritten.
@@ -330,6 +270,24 @@ struct Staging {
 
 }  // namespace
 
+// Block-path surfaces swept by one kernel instance: rows [first, first +
+// count) of the descriptor table, blocks numbered from 0 within the shape.
+struct Shape {
+    const Variant *variant = nullptr;
+    int xmode = 1;
+    int first = 0, count = 0;
+    int total_blocks = 0;
+    int *d_owner = nullptr;  // block -> row within the shape (count > 1)
+};
+
+// A launch choice for one surface: kernel variant, block order and sweeps
+// per captured graph (none of them changes results).
+struct Choice {
+    const Variant *v = nullptr;
+    int xmode = 1;
+    int graph_k = 0;
+};
+
 // ---------------------------------------------------------------------------
 // A group of surfaces sharing one D: the common core of the single-surface,
 // batch and engine front ends.
@@ -341,17 +299,19 @@ struct SurfaceGroup {
     hipStream_t stream = nullptr;
     bool failed = false;
     std::vector<SurfDev> host;         // host mirror (t, t_end kept current)
+    std::vector<long long> dev_t_end;  // t_end values last uploaded
     std::vector<long long> max_h0, t0; // per surface
     SurfDev *d_desc = nullptr;
     long long *d_acc = nullptr;        // kAccWords per block-path surface
     std::vector<int32_t *> readout;    // 16-bit storage: int32[L^2] device scratch per surface
     long long *d_ps = nullptr;         // power sums: per-workgroup partials, then the result
-    int *d_queue = nullptr;            // blocks handed to the wider fallback launch
-    int *d_owner = nullptr;            // block -> descriptor index (several surfaces only)
+    int xmode = 1;                     // workgroup -> block order (rsosk::block_map) without a choice
+    std::vector<Shape> shapes;         // block-path surfaces by kernel instance
+    std::vector<Choice> want;          // per surface: a tuned launch choice (or none); read by setup()
+    std::vector<int> rows;             // device-table row -> surface index
     std::vector<int> lds_idx, blk_idx; // surfaces on each path
     int *d_lds_idx = nullptr;
-    const Variant *variant = nullptr;
-    int total_blocks = 0;
+    int graph_k = kGraphSweeps;        // sweeps per captured graph
     size_t lds_bytes = 0;
     Staging staging;
     hipGraphExec_t graph = nullptr;
@@ -369,7 +329,9 @@ struct SurfaceGroup {
     }
 
     // Builds the descriptor table (host side must be filled: buf, log, L, N,
-    // key, t, t_end).  Picks a block variant for the block-path surfaces.
+    // key, t, t_end).  Groups the block-path surfaces by kernel instance:
+    // each surface's tuned choice where want[] holds one for every
+    // block-path surface, else one first-fit variant for all of them.
     rsos_status setup()
     {
         const int n = (int)host.size();
@@ -381,57 +343,85 @@ struct SurfaceGroup {
                 if (((uintptr_t)host[i].buf[k] & 15) != 0)
                     return fail(RSOS_E_INVAL, "height buffers must be 16-byte aligned");
         }
-        if (!blk_idx.empty()) {
-            variant = pick_variant(D, LN, packed, sched == 1);
-            if (!variant) return fail(RSOS_E_INVAL, "no tile-block shape fits these lattice sizes");
-        }
         if (packed && !lds_idx.empty()) return fail(RSOS_E_INVAL, "16-bit storage needs the tile-block path");
-        // block path surfaces first in the table, sorted by block_start
-        long long blocks = 0;
-        for (int i : blk_idx) {
-            SurfDev &s = host[i];
-            const int T = s.L / D;
-            s.nbx = T / variant->TX;
-            s.nblocks = s.nbx * (T / variant->TY);
-            s.block_start = (int)blocks;
-            blocks += s.nblocks;
-            if (blocks > (1ll << 30)) return fail(RSOS_E_INVAL, "too many tile blocks");
+        if (const char *xm = getenv("RSOS_XMODE")) xmode = atoi(xm) == 0 ? 0 : atoi(xm) == 2 ? 2 : 1;
+        bool tuned = !blk_idx.empty() && want.size() == host.size();
+        for (int i : blk_idx) tuned = tuned && want[i].v != nullptr;
+        std::vector<std::vector<int>> members;
+        if (tuned) {
+            for (int i : blk_idx) {
+                size_t g = 0;
+                while (g < shapes.size() && !(shapes[g].variant == want[i].v && shapes[g].xmode == want[i].xmode)) ++g;
+                if (g == shapes.size()) {
+                    shapes.push_back(Shape());
+                    shapes.back().variant = want[i].v;
+                    shapes.back().xmode = want[i].xmode;
+                    members.emplace_back();
+                }
+                members[g].push_back(i);
+            }
+            graph_k = 0;
+            for (int i : blk_idx) graph_k = std::max(graph_k, want[i].graph_k);
+            if (graph_k < 1) graph_k = kGraphSweeps;
+        } else if (!blk_idx.empty()) {
+            const Variant *v = pick_variant(D, LN, packed, sched == 1);
+            if (!v) return fail(RSOS_E_INVAL, "no tile-block shape fits these lattice sizes");
+            shapes.push_back(Shape());
+            shapes.back().variant = v;
+            shapes.back().xmode = xmode;
+            members.push_back(blk_idx);
         }
-        total_blocks = (int)blocks;
+        // rows: each shape's surfaces in turn (block numbers restart at 0 in
+        // every shape), then the LDS-path surfaces
+        rows.clear();
+        for (size_t g = 0; g < shapes.size(); ++g) {
+            Shape &sh = shapes[g];
+            sh.first = (int)rows.size();
+            sh.count = (int)members[g].size();
+            long long blocks = 0;
+            for (int i : members[g]) {
+                SurfDev &sd = host[i];
+                const int T = sd.L / D;
+                sd.nbx = T / sh.variant->TX;
+                sd.nblocks = sd.nbx * (T / sh.variant->TY);
+                sd.block_start = (int)blocks;
+                blocks += sd.nblocks;
+                if (blocks > (1ll << 30)) return fail(RSOS_E_INVAL, "too many tile blocks");
+                rows.push_back(i);
+            }
+            sh.total_blocks = (int)blocks;
+            if (sh.xmode == 2 && !(sh.count == 1 && host[members[g][0]].nbx % 8 == 0)) sh.xmode = 1;
+        }
+        const int nblk_rows = (int)rows.size();
         for (int i : lds_idx) {
             host[i].nbx = 0;
             host[i].nblocks = 0;
             host[i].block_start = 1 << 30;  // never matched by a block workgroup
+            rows.push_back(i);
         }
         rsos_status st;
         if ((st = dev_alloc((void **)&d_desc, sizeof(SurfDev) * n)) != RSOS_OK) return st;
-        if (!blk_idx.empty()) {
-            const size_t bytes = sizeof(long long) * rsosk::kAccWords * blk_idx.size();
+        if (nblk_rows) {
+            const size_t bytes = sizeof(long long) * rsosk::kAccWords * nblk_rows;
             if ((st = dev_alloc((void **)&d_acc, bytes)) != RSOS_OK) return st;
             HIP_TRY(hipMemset(d_acc, 0, bytes));
-            for (size_t k = 0; k < blk_idx.size(); ++k)
-                host[blk_idx[k]].acc = d_acc + rsosk::kAccWords * k;
-            if ((st = dev_alloc((void **)&d_queue, sizeof(int) * (1 + (size_t)total_blocks))) != RSOS_OK)
-                return st;
-            HIP_TRY(hipMemset(d_queue, 0, sizeof(int)));
-            if (blk_idx.size() > 1) {
-                // owner of every block: block-path surfaces sit first in the
-                // device table, in blk_idx order
-                std::vector<int> own((size_t)total_blocks);
-                for (size_t k = 0; k < blk_idx.size(); ++k) {
-                    const SurfDev &sd = host[blk_idx[k]];
-                    for (int b = 0; b < sd.nblocks; ++b) own[(size_t)sd.block_start + b] = (int)k;
-                }
-                if ((st = dev_alloc((void **)&d_owner, sizeof(int) * own.size())) != RSOS_OK) return st;
-                HIP_TRY(hipMemcpy(d_owner, own.data(), sizeof(int) * own.size(), hipMemcpyHostToDevice));
+            for (int r = 0; r < nblk_rows; ++r) host[rows[r]].acc = d_acc + rsosk::kAccWords * r;
+        }
+        for (Shape &sh : shapes) {
+            if (sh.count < 2) continue;
+            // owner of every block of the shape: its row within the shape
+            std::vector<int> own((size_t)sh.total_blocks);
+            for (int k = 0; k < sh.count; ++k) {
+                const SurfDev &sd = host[rows[sh.first + k]];
+                for (int b = 0; b < sd.nblocks; ++b) own[(size_t)sd.block_start + b] = k;
             }
+            if ((st = dev_alloc((void **)&sh.d_owner, sizeof(int) * own.size())) != RSOS_OK) return st;
+            HIP_TRY(hipMemcpy(sh.d_owner, own.data(), sizeof(int) * own.size(), hipMemcpyHostToDevice));
         }
         if (!lds_idx.empty()) {
             if ((st = dev_alloc((void **)&d_lds_idx, sizeof(int) * lds_idx.size())) != RSOS_OK) return st;
-            // device-table positions of the LDS-path surfaces (they follow
-            // the block-path ones)
             std::vector<int> pos(lds_idx.size());
-            for (size_t k = 0; k < pos.size(); ++k) pos[k] = (int)(blk_idx.size() + k);
+            for (size_t k = 0; k < pos.size(); ++k) pos[k] = nblk_rows + (int)k;
             HIP_TRY(hipMemcpy(d_lds_idx, pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice));
             int maxL = 0;
             for (int i : lds_idx) maxL = std::max(maxL, host[i].L);
@@ -440,32 +430,34 @@ struct SurfaceGroup {
         return upload_all();
     }
 
-    // The block kernel binary-searches descriptors by block_start, so the
-    // device table lists block-path surfaces first in block order.
-    std::vector<int> order() const
-    {
-        std::vector<int> o(blk_idx);
-        o.insert(o.end(), lds_idx.begin(), lds_idx.end());
-        return o;
-    }
-
     rsos_status upload_all()
     {
         const int n = (int)host.size();
         rsos_status st = staging.ensure(sizeof(SurfDev) * n);
         if (st != RSOS_OK) return st;
-        std::vector<int> o = order();
         SurfDev *h = (SurfDev *)staging.host;
-        for (int k = 0; k < n; ++k) h[k] = host[o[k]];
+        for (int k = 0; k < n; ++k) h[k] = host[rows[k]];
         return staging.copy_to(d_desc, sizeof(SurfDev) * n, stream);
     }
 
-    rsos_status set_t_end(const std::vector<long long> &t_end)
+    // Sets every surface's end time for the next launch_sweeps(n).  A
+    // block-path surface that advances by all n sweeps needs no bound (the
+    // launch count is the bound) and keeps an unbounded t_end on the device,
+    // so a run of such calls rewrites nothing; the others, and LDS-path
+    // surfaces (which run to their t_end in one launch), get their exact
+    // t_end.  A rewrite uploads the whole (small) table, t included: the
+    // host mirror of t is exact, since sweep counts are deterministic.
+    rsos_status set_t_end(const std::vector<long long> &t_end, long long n)
     {
-        for (size_t i = 0; i < host.size(); ++i) host[i].t_end = t_end[i];
-        // only t_end changes; rewriting the whole (small) table keeps t in
-        // sync too, since the host mirror of t is exact (sweep counts are
-        // deterministic)
+        bool changed = dev_t_end.size() != host.size();
+        for (size_t i = 0; i < host.size(); ++i) {
+            const bool blk = !uses_lds(host[i].L);
+            host[i].t_end = (blk && t_end[i] - host[i].t == n) ? kNoEnd : t_end[i];
+            changed = changed || host[i].t_end != dev_t_end[i];
+        }
+        if (!changed) return RSOS_OK;
+        dev_t_end.resize(host.size());
+        for (size_t i = 0; i < host.size(); ++i) dev_t_end[i] = host[i].t_end;
         return upload_all();
     }
 
@@ -478,9 +470,9 @@ struct SurfaceGroup {
         }
         if (blk_idx.empty()) return RSOS_OK;
         long long left = n;
-        if (stream != nullptr && n >= 2 * kGraphSweeps && !timing) {
+        if (stream != nullptr && n >= 2 * graph_k && !timing) {
             if (!graph) {
-                rsos_status st = capture_graph(kGraphSweeps);
+                rsos_status st = capture_graph(graph_k);
                 if (st != RSOS_OK) return st;
             }
             while (left >= graph_sweeps) {
@@ -495,15 +487,16 @@ struct SurfaceGroup {
         return RSOS_OK;
     }
 
-    // the tile-block sweep proper: one workgroup per block, then (int8
-    // staging) the queued blocks with wider staging
+    // the tile-block sweep proper: one workgroup per block, the whole sweep
+    // in one launch per kernel instance
     void launch_block_sweep()
     {
-        const int n = (int)blk_idx.size();
-        BlockLaunch main = packed ? variant->launch16 : sched == 1 ? variant->launch_dt : variant->launch;
-        BlockLaunch fb = packed ? variant->fallback16 : sched == 1 ? variant->fallback_dt : variant->fallback;
-        main(dim3(total_blocks), stream, d_desc, n, d_owner, d_queue);
-        if (fb) fb(dim3((unsigned)std::min(total_blocks, kFallbackGrid)), stream, d_desc, n, d_owner, d_queue);
+        for (const Shape &sh : shapes) {
+            const Variant *v = sh.variant;
+            BlockLaunch k = packed ? v->launch16 : sched == 1 ? v->launch_dt : v->launch;
+            const int nbx = sh.count == 1 ? host[rows[sh.first]].nbx : 0;
+            k(dim3(sh.total_blocks), stream, d_desc + sh.first, sh.count, sh.d_owner, sh.xmode, nbx);
+        }
     }
 
     rsos_status enqueue_one()
@@ -518,9 +511,6 @@ struct SurfaceGroup {
         launch_block_sweep();
         HIP_TRY(hipGetLastError());
         if (timing) HIP_TRY(hipEventRecord(e1, stream));
-        hipLaunchKernelGGL(rsosk::reduce_acc, dim3((unsigned)blk_idx.size()), dim3(64), 0, stream,
-                           d_desc, d_queue);
-        HIP_TRY(hipGetLastError());
         return RSOS_OK;
     }
 
@@ -528,11 +518,7 @@ struct SurfaceGroup {
     {
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < k; ++i) {
-            launch_block_sweep();
-            hipLaunchKernelGGL(rsosk::reduce_acc, dim3((unsigned)blk_idx.size()), dim3(64), 0,
-                               stream, d_desc, d_queue);
-        }
+        for (int i = 0; i < k; ++i) launch_block_sweep();
         HIP_TRY(hipStreamEndCapture(stream, &g));
         HIP_TRY(hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));
         HIP_TRY(hipGraphDestroy(g));
@@ -720,6 +706,11 @@ struct rsos_batch {
     SurfaceGroup g;
 };
 
+// ---------------------------------------------------------------------------
+// autotuner of the launch knobs -- see rsos_tune.inc
+// ---------------------------------------------------------------------------
+#include "rsos_tune.inc"
+
 #define CHECK_HANDLE(h, grp)                                                           \
     do {                                                                               \
         if (!(h)) return fail(RSOS_E_INVAL, "NULL handle");                           \
@@ -752,6 +743,13 @@ const char *rsos_strerror(rsos_status st)
 }
 
 const char *rsos_last_error(void) { return g_last_error.c_str(); }
+
+rsos_status rsos_debug_fail(int32_t after)
+{
+    if (after < 0) return fail(RSOS_E_INVAL, "after < 0");
+    rsosh::g_fail_countdown = after;
+    return RSOS_OK;
+}
 
 void rsos_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
@@ -809,6 +807,11 @@ rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, in
     g.host.push_back(d);
     g.max_h0.push_back(max_h);
     g.t0.push_back(t0);
+    if (tuning_wanted(p) && !uses_lds(p->L)) {
+        Choice c;
+        if ((st = tuned_choice(p, 0, &c)) != RSOS_OK) { g.destroy(); delete s; return st; }
+        g.want.assign(1, c);
+    }
     if ((st = mark(g, g.setup())) != RSOS_OK) { g.destroy(); delete s; return st; }
     // initial state into the buffer of parity t0
     if ((st = g.load_initial(0, h0_host, s1)) != RSOS_OK) { g.destroy(); delete s; return st; }
@@ -827,7 +830,7 @@ rsos_status rsos_sweep(rsos_surface *s, int64_t n_mcs)
     if (t + n_mcs > (1ll << 32)) return fail(RSOS_E_INVAL, "sweep index would exceed 2^32");
     rsos_status st = check_overflow(s->p, g.max_h0[0], t + n_mcs - g.t0[0]);
     if (st != RSOS_OK) return st;
-    if ((st = mark(g, g.set_t_end({t + n_mcs}))) != RSOS_OK) return st;
+    if ((st = mark(g, g.set_t_end({t + n_mcs}, n_mcs))) != RSOS_OK) return st;
     if ((st = mark(g, g.launch_sweeps(n_mcs))) != RSOS_OK) return st;
     g.host[0].t = t + n_mcs;
     return RSOS_OK;
@@ -888,19 +891,14 @@ rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len)
     CHECK_HANDLE(s, s->g);
     if (!buf || len < 1) return fail(RSOS_E_INVAL, "bad buffer");
     const SurfaceGroup &g = s->g;
-    if (g.variant && g.packed)
-        snprintf(buf, (size_t)len, "block_sweep16<%d,%d,%d,%d,uint8>", g.variant->D, g.variant->TX,
-                 g.variant->TY, g.variant->NT);
-    else if (g.variant && g.sched == 1)
-        snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s,dt>", g.variant->D, g.variant->TX,
-                 g.variant->TY, g.variant->NT,
-                 g.variant->elem == 1 ? "int8" : g.variant->elem == 2 ? "int16" : "int32");
-    else if (g.variant)
-        snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s>", g.variant->D, g.variant->TX,
-                 g.variant->TY, g.variant->NT,
-                 g.variant->elem == 1 ? "int8" : g.variant->elem == 2 ? "int16" : "int32");
+    const Variant *v = g.shapes.empty() ? nullptr : g.shapes[0].variant;
+    if (v && g.packed)
+        snprintf(buf, (size_t)len, "block_sweep16<%d,%d,%d,%d,0>", v->D, v->TX, v->TY, v->NT);
+    else if (v)
+        snprintf(buf, (size_t)len, "block_sweep<%d,%d,%d,%d,%s,%d>", v->D, v->TX, v->TY, v->NT,
+                 v->elem == 1 ? "int8,int16" : v->elem == 2 ? "int16,void" : "int32,void", g.sched);
     else
-        snprintf(buf, (size_t)len, "lds_run<%d>", g.D);
+        snprintf(buf, (size_t)len, "lds_run<%d,256,%d>", g.D, g.sched);
     return RSOS_OK;
 }
 
@@ -975,6 +973,30 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
         g.max_h0.push_back(0);
         g.t0.push_back(0);
     }
+    if (tuning_wanted(&p[0])) {
+        // one tuned choice per (L, N) class, grouped into kernel instances,
+        // unless one variant for all times faster on this mix
+        g.want.assign(n, Choice());
+        std::vector<std::pair<int, int>> LN;
+        std::vector<Choice> plan;
+        for (int i = 0; i < n; ++i) {
+            if (uses_lds(p[i].L)) continue;
+            if ((st = tuned_choice(&p[i], 1, &g.want[i])) != RSOS_OK) {
+                g.destroy();
+                delete b;
+                return st;
+            }
+            LN.push_back({p[i].L, p[i].N});
+            plan.push_back(g.want[i]);
+        }
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            st = batch_plan(p[0].D, (int)p[0].flags, LN, &plan);
+        }
+        if (st != RSOS_OK) { g.destroy(); delete b; return st; }
+        for (int i = 0, k = 0; i < n; ++i)
+            if (!uses_lds(p[i].L)) g.want[i] = plan[k++];
+    }
     if ((st = mark(g, g.setup())) != RSOS_OK) { g.destroy(); delete b; return st; }
     for (int i = 0; i < n; ++i)
         if ((st = g.load_initial(i, nullptr, 0)) != RSOS_OK || (st = g.init_record(i, 0, 0)) != RSOS_OK) {
@@ -1004,7 +1026,7 @@ rsos_status rsos_batch_sweep(rsos_batch *b, const int64_t *n_mcs, int64_t n_all)
     }
     if (most == 0) return RSOS_OK;
     rsos_status st;
-    if ((st = mark(g, g.set_t_end(t_end))) != RSOS_OK) return st;
+    if ((st = mark(g, g.set_t_end(t_end, most))) != RSOS_OK) return st;
     if ((st = mark(g, g.launch_sweeps(most))) != RSOS_OK) return st;
     for (int i = 0; i < n; ++i) g.host[i].t = t_end[i];
     return RSOS_OK;

@@ -22,14 +22,13 @@
 //                in the ring, and the update is a pure function of them),
 //                runs phase 1 on the block, stores the block into the output
 //                buffer and adds its (S1, S2, A) increments to one of the
-//                surface's 64 accumulator slots.  Both phases of a sweep cost
-//                one read and one write of every site.  int8 blocks whose
-//                range does not fit are queued for a second launch of the
-//                same kernel shape with wider staging.
+//                surface's 64 accumulator slots; the surface's last block
+//                folds them into the per-sweep log.  A sweep, sums included,
+//                is one launch and costs one read and one write of every
+//                site.  An int8 block whose range does not fit is swept
+//                again by the same workgroup as int16 sub-blocks.
 //   block_sweep16  the same on heights kept in HBM as 16-bit residues
 //                (half the bytes per sweep) when N L <= 32766.
-//   reduce_acc   folds each surface's accumulators into its per-sweep log,
-//                clears them, keeps floor(S1 / L^2) and advances its time.
 //   lds_run      a whole small surface (L^2 * 4 bytes fits in LDS) lives in
 //                one workgroup's LDS for many sweeps; no per-sweep launch.
 #pragma once
@@ -74,15 +73,20 @@ __host__ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1
 
 // ---------------------------------------------------------------------------
 // Per-surface state shared by the kernels.  Lives in device memory; the
-// host writes it at setup and sets t_end before a run; the reduce (or
-// lds_run) kernel advances t.
+// host writes it at setup and sets t_end before a run; the sweep's last
+// block (or lds_run) advances t.
 // ---------------------------------------------------------------------------
 constexpr int kAccSlots = 64;  // per-surface spread of the (S1, S2, A) atomics
 // Per-surface accumulator area: 3 * kAccSlots words of increments, then
-// word kMeanWord = floor(S1 / L^2) of the current time (kept by reduce_acc;
-// the 16-bit storage mode recovers true heights from it).
+// word kMeanWord = floor(S1 / L^2) of the current time (kept by the sweep's
+// last block; the 16-bit storage mode recovers true heights from it, every
+// block reads it) and, in a 128-byte line of its own so that the blocks'
+// atomic additions to it do not stall those reads, word kDoneWord, the
+// blocks of the running sweep that have committed.  All words but
+// kMeanWord are zero between sweeps.  Areas are 128-byte aligned.
 constexpr int kMeanWord = 3 * kAccSlots;
-constexpr int kAccWords = 3 * kAccSlots + 4;
+constexpr int kDoneWord = kMeanWord + 16;
+constexpr int kAccWords = kDoneWord + 16;
 
 // Lattice pointers reach the kernels through descriptors in memory, so the
 // compiler sees generic pointers and would emit flat memory instructions
@@ -123,10 +127,6 @@ struct SurfDev {
     int nblocks;          // blocks of this surface (block path)
     int block_start;      // first global block index of this surface
 };
-
-// Blocks whose staged heights would not fit the narrow LDS element type are
-// handed to a second launch with a wider type: queue[0] counts them, queue[1..]
-// lists their global block indices.  reduce_acc clears the count.
 
 template <int D>
 struct TileBits {
@@ -217,22 +217,6 @@ __device__ __forceinline__ void tile_attempts(E *lds, int base, uint32_t tile_id
         for (int k = 0; k < TAIL; ++k)
             attempt<D, P, E, Q>(lds, base, (r.v[k / TB::F] >> ((k % TB::F) * TB::B)) & MASK, N, acc, q);
     }
-}
-
-// XCD-aware renumbering: the dispatcher hands consecutive workgroup ids to
-// the 8 XCDs in turn.  Renumber so that each XCD takes runs of 16
-// consecutive blocks (left and right neighbours share that XCD's L2 for
-// their ring columns) while the 8 XCDs together still walk the lattice in
-// memory order (one moving front through HBM instead of 8 separate ones,
-// which measured 8% faster than contiguous per-XCD ranges).  Blocks beyond
-// the last whole group of 8 x 16 keep their own number.
-__device__ __forceinline__ int xcd_remap(int wg, int n)
-{
-    constexpr int C = 16;
-    const int full = n - n % (8 * C);
-    if (wg >= full) return wg;
-    const int x = wg & 7, j = wg >> 3;
-    return (j / C) * (8 * C) + x * C + (j % C);
 }
 
 __device__ __forceinline__ void wave_reduce3(long long &a, long long &b, long long &c)
@@ -441,83 +425,178 @@ __device__ __forceinline__ void sweep_phases(E *lds, int off, int bx, int by, in
         block_phases_dt<D, TX, TY, NT, RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
 }
 
-// Adds the block's increments (A, 2 sum(base + c) + A, A) of S1, S2 and
-// the accepted count to one of the surface's accumulator slots (q = sum of
-// the staged values c before the accepted deposits; base is the height that
-// staged value 0 stands for).  Ends with a barrier (LDS is reused by the next
-// queued block).
-template <int NT, typename Q>
-__device__ __forceinline__ void block_commit(const SurfDev &d, int b, int acc, Q q, long long base)
+// ---------------------------------------------------------------------------
+// End of a sweep.  Every block adds its increments (A, sum(2h + 1) over its
+// accepted deposits, A) of S1, S2 and the accepted count to one of the
+// surface's 64 accumulator slots and counts itself in the surface's done
+// word; the block that completes the count folds the slots into the record
+// of time t + 1 (the record of t plus the increments), clears them, keeps
+// floor(S1 / L^2) and advances the surface's time.  So one launch is a
+// whole sweep, and the sums are exact whatever order the blocks finish in.
+// All of it uses device-scope atomics without fences (an acquire or release
+// at device scope would write back or invalidate the XCD's whole L2 in
+// every block): a block counts itself only after its three slot additions
+// have been performed (it waits for them), and the last block reads the
+// slots with device-scope atomic loads.  Its plain stores (time, log
+// record, mean) are read by later launches only.
+// ---------------------------------------------------------------------------
+
+// Wave 0 of the block that completed the count.
+__device__ __forceinline__ void finish_sweep(SurfDev &d, long long t)
 {
-    long long A = acc, S2inc = (long long)q, unused = 0;
-    block_reduce3<NT>(A, S2inc, unused);
-    if (threadIdx.x == 0) {
-        S2inc = 2ll * S2inc + A + 2ll * base * A;
-        gu64 *a = (gu64 *)(d.acc + 3 * (b & (kAccSlots - 1)));
-        __hip_atomic_fetch_add(a + 0, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(a + 1, (unsigned long long)S2inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(a + 2, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int lane = threadIdx.x;  // < 64
+    gu64 *a = (gu64 *)(d.acc + 3 * lane);
+    long long x = (long long)__hip_atomic_load(a + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long long y = (long long)__hip_atomic_load(a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long long z = (long long)__hip_atomic_load(a + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a + 0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a + 1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a + 2, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wave_reduce3(x, y, z);
+    if (lane == 0) {
+        const gi64 *prev = (const gi64 *)(d.log + 3 * (t % d.log_cap));
+        gi64 *e = (gi64 *)(d.log + 3 * ((t + 1) % d.log_cap));
+        const long long s1 = prev[0] + x, s2 = prev[1] + y;
+        e[0] = s1;
+        e[1] = s2;
+        e[2] = z;
+        *(gi64 *)(d.acc + kMeanWord) = s1 / ((long long)d.L * d.L);
+        __hip_atomic_store((gu64 *)(d.acc + kDoneWord), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *(gi64 *)&d.t = t + 1;
     }
-    __syncthreads();
 }
 
+// a = this thread's accepted count, s2 = its share of the S2 increment.
+// Called by the whole workgroup once its sums are final (before its
+// stores: nothing here depends on them).
+template <int NT>
+__device__ __forceinline__ void commit_sweep(SurfDev &d, int b, long long a, long long s2, long long t)
+{
+    __shared__ int s_last;
+    long long unused = 0;
+    block_reduce3<NT>(a, s2, unused);
+    if (threadIdx.x == 0) {
+        gu64 *slot = (gu64 *)(d.acc + 3 * (b & (kAccSlots - 1)));
+        __hip_atomic_fetch_add(slot + 0, (unsigned long long)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(slot + 1, (unsigned long long)s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(slot + 2, (unsigned long long)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the three additions are performed before the block is counted
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const unsigned long long prev = __hip_atomic_fetch_add((gu64 *)(d.acc + kDoneWord), 1ull,
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev + 1 == (unsigned long long)d.nblocks;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x < 64) finish_sweep(d, t);
+}
+
+// Workgroup -> global block.  Mode 1: the dispatcher hands consecutive
+// workgroup ids to the 8 XCDs in turn; each XCD takes runs of 16 consecutive
+// blocks (left and right neighbours share its L2 for their ring columns)
+// while the 8 XCDs together walk the lattice in memory order; blocks beyond
+// the last whole group of 8 x 16 keep their number.  Mode 2 (one surface,
+// nbx % 8 == 0): XCD x owns the block columns [x nbx/8, (x+1) nbx/8) and
+// walks them row by row, so a block's upper and lower neighbours, whose
+// regions overlap its ring rows, run on the same XCD; all XCDs still move
+// down the lattice together.  Mode 0: identity.
+__device__ __forceinline__ int block_map(int wg, int n, int mode, int nbx)
+{
+    if (mode == 1) {
+        constexpr int C = 16;
+        const int full = n - n % (8 * C);
+        if (wg >= full) return wg;
+        const int x = wg & 7, j = wg >> 3;
+        return (j / C) * (8 * C) + x * C + (j % C);
+    }
+    if (mode == 2) {
+        const int sw = nbx >> 3, x = wg & 7, j = wg >> 3;
+        return (j / sw) * nbx + x * sw + j % sw;
+    }
+    return wg;
+}
+
+// Where a block's staging does not fit its narrow element type, the same
+// workgroup sweeps it again as SX x SY sub-blocks with the wide type EW.
+// The tile block shape never changes results (each sub-block recomputes the
+// ring tiles it reads), so the sub-blocks reproduce the block's bits.  The
+// split is the smallest one whose wide staging fits the LDS of the narrow
+// one (sub-blocks keep whole checkerboard pairs: even tile counts, and rows
+// the store can tile); with no such split the LDS is the larger of the two.
+template <int D, int TX, int TY, int NT, int CPC, int ES, int EWS>
+struct WideSplit {
+    template <int SX, int SY>
+    static constexpr bool ok()
+    {
+        return TX % SX == 0 && TY % SY == 0 && (TX / SX) % 2 == 0 && (TY / SY) % 2 == 0 &&
+               ((TX / SX) * D) % CPC == 0 && NT % ((TX / SX) * D / CPC) == 0;
+    }
+    template <int SX, int SY>
+    static constexpr int bytes()
+    {
+        using G = BlockGeom<D, TX / SX, TY / SY, CPC>;
+        return G::RWL * G::RH * EWS;
+    }
+    static constexpr int MAIN = BlockGeom<D, TX, TY, CPC>::RWL * BlockGeom<D, TX, TY, CPC>::RH * ES;
+    static constexpr int pick()  // 0: 1x1, 1: 2x1, 2: 1x2, 3: 2x2
+    {
+        if (EWS == 0) return 0;
+        if (bytes<1, 1>() <= MAIN) return 0;
+        if (ok<2, 1>() && bytes<2, 1>() <= MAIN) return 1;
+        if (ok<1, 2>() && bytes<1, 2>() <= MAIN) return 2;
+        if (ok<2, 2>() && bytes<2, 2>() <= MAIN) return 3;
+        if (ok<2, 2>()) return 3;
+        return 0;
+    }
+    static constexpr int K = pick();
+    static constexpr int SX = (K & 1) ? 2 : 1, SY = (K & 2) ? 2 : 1;
+    static constexpr int WIDE = EWS == 0 ? 0 : bytes<(K & 1) ? 2 : 1, (K & 2) ? 2 : 1>();
+    static constexpr int BYTES = MAIN > WIDE ? MAIN : WIDE;
+};
+
+template <typename EW> struct WideSize { static constexpr int v = sizeof(EW); };
+template <> struct WideSize<void> { static constexpr int v = 0; };
+
+// Waves per SIMD that the LDS of a kernel with a wide path allows (160 KB
+// per CU, 4 SIMDs, at most 7).  For D = 8 the register budget is held to
+// it, so that the rarely taken wide path (whose registers the compiler then
+// spills, in that path only) does not lower the occupancy of the main one;
+// for the other domain sizes the budget would force spills into the main
+// path, and the compiler's own allocation is kept.
+template <int D, int TX, int TY, int NT, int CPC, int ES, int EWS>
+struct WideOcc {
+    static constexpr int lds = WideSplit<D, TX, TY, NT, CPC, ES, EWS>::BYTES + 64;
+    static constexpr int w = (163840 / lds) * (NT / 64) / 4;
+    static constexpr int v = (EWS == 0 || D != 8) ? 1 : (w < 1 ? 1 : (w > 7 ? 7 : w));
+};
+
 // ---------------------------------------------------------------------------
-// block_sweep: one sweep for every active surface of the descriptor table,
-// int32 heights in HBM.
-// Requirements checked on the host: T % TX == 0, T % TY == 0, TX and TY
-// even, RWL <= L, RH <= L, 16-byte aligned buffers, and for E = int16
+// One region (a TX x TY tile block of the shifted frame, block coordinates
+// (bx, by) in units of that shape) of sweep s, int32 heights in HBM: stage
+// the region and its ring of D+1 sites in LDS, run both phases, store the
+// region's tiles.  With a narrow element type that is range-checked (int8)
+// it returns false, having written nothing, when some staged value could
+// leave the type during the sweep.  Adds the thread's accepted count to ca
+// and its share of the S2 increment to cs2.
+// Host requirements: T % TX == 0, T % TY == 0, TX and TY even, RWL <= L,
+// RH <= L, 16-byte aligned buffers, and for E = int16
 // N * (RW + RH + 4) + D^2 <= 32767 (every staged value stays within int16
 // of the reference: any two region sites are joined by a path of at most
 // RW + RH - 2 bonds, each of height difference <= N, and no site gains
 // more than D^2 in a sweep).
-// The block's accumulator slot receives (A, sum(2h+1), A) over its accepted
-// deposits (h the height before the deposit): the sweep's increments of S1
-// and S2 (exact), from which reduce_acc advances the surface's sums.
 // ---------------------------------------------------------------------------
-template <typename E>
-struct StageLimits {
-    // staged values are kept as E relative to the block reference; int8
-    // blocks check their range at load time, wider types are chosen by the
-    // host so that every value fits
-    static constexpr bool checked = sizeof(E) == 1;
-};
-
-// FALLBACK = false: every workgroup takes one block (grid = all blocks of
-// the table); an int8 workgroup whose block does not fit queues it and
-// stops.  FALLBACK = true: workgroups walk the queue of the preceding
-// int8 launch.
-template <int D, int TX, int TY, int NT, typename E, bool FALLBACK, int SCHED = 0>
-__global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ descs, int nsurf,
-                                                  const int *__restrict__ owner, int *__restrict__ queue)
+template <int D, int TX, int TY, int NT, typename E, int SCHED, int U = 8>
+__device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by, long long t, int ox, int oy,
+                                             int *s_bad, long long &ca, long long &cs2, bool commit_here, int b)
 {
+    const uint32_t s = (uint32_t)t;
     using G = BlockGeom<D, TX, TY>;
     using Q = typename std::conditional<sizeof(E) <= 2, int, long long>::type;
-    __shared__ __attribute__((aligned(16))) E lds[G::RWL * G::RH];
-    __shared__ int s_bad;
-
-    if (StageLimits<E>::checked) {
-        if (threadIdx.x == 0) s_bad = 0;
-        __syncthreads();
-    }
-    const int nq = FALLBACK ? queue[0] : 1;
-    for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
-    const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
-    const SurfDev &d = descs[find_surface(descs, nsurf, owner, lb)];
-    const long long t = d.t;
-    if (t >= d.t_end) continue;
-
+    constexpr bool checked = sizeof(E) == 1;
     const int L = d.L, N = d.N, T = d.T;
-    const uint32_t s = (uint32_t)t;
     const uint32_t k0 = d.key0, k1 = d.key1;
-    const gint32 *__restrict__ hin = as_global(d.buf[t & 1]);
-    gint32 *__restrict__ hout = as_global(d.buf[(t + 1) & 1]);
+    const gint32 *__restrict__ hin = as_global(d.buf[s & 1u]);
+    gint32 *__restrict__ hout = as_global(d.buf[(s + 1u) & 1u]);
 
-    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
-    const int ox = (int)(org.v[0] % (2u * D));
-    const int oy = (int)(org.v[1] % (2u * D));
-
-    const int b = lb - d.block_start;
-    const int bx = b % d.nbx, by = b / d.nbx;
     int gx0 = ox + bx * TX * D - G::RING;
     int gy0 = oy + by * TY * D - G::RING;
     if (gx0 < 0) gx0 += L;
@@ -532,7 +611,6 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
     // thread; chunk i sits at region row i / CH, chunk column i % CH
     {
         constexpr int NCH = G::CH * G::RH;
-        constexpr int U = 8;
         constexpr int FULL = NCH / (NT * U);  // groups in which every thread has U chunks
         auto fetch = [&](int i) {
             const int r = i / G::CH, cc = i - r * G::CH;
@@ -546,7 +624,7 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
         auto stage = [&](int i, const int4 &v) {
             const int r = i / G::CH, cc = i - r * G::CH;
             lds_put4<E>(lds + r * G::RWL + 4 * cc, v, ref);
-            if (StageLimits<E>::checked) {
+            if (checked) {
                 vmin = min(vmin, min(min(v.x, v.y), min(v.z, v.w)));
                 vmax = max(vmax, max(max(v.x, v.y), max(v.z, v.w)));
             }
@@ -571,26 +649,26 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
                 if (i0 + u * NT < NCH) stage(i0 + u * NT, v[u]);
         }
     }
-    if (StageLimits<E>::checked) {
+    if (checked) {
         // every value of the sweep stays in [min, max + N D]: heights never
         // decrease, and a tile site is never more than N D/2 above the
         // frozen sites around its tile (a path of at most D/2 bonds), whose
         // values grow by at most N D/2 in the first phase
-        if (vmin - ref < -128 || (long long)vmax - ref + (long long)N * D > 127) s_bad = 1;
+        if (vmin - ref < -128 || (long long)vmax - ref + (long long)N * D > 127) *s_bad = 1;
     }
     __syncthreads();
-    if (StageLimits<E>::checked && s_bad) {
-        if (threadIdx.x == 0) {
-            const int k = atomicAdd(queue, 1);
-            queue[1 + k] = lb;
-        }
-        continue;  // uniform: the whole workgroup leaves this block
-    }
+    if (checked && *(volatile int *)s_bad) return false;  // uniform: the whole workgroup
 
     const int off = G::RING + cpad;  // LDS column of block column 0
     int acc = 0;
     Q q = 0;
     sweep_phases<SCHED, D, TX, TY, NT, G::RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    // a deposit on h raises S2 by 2h + 1; the staged value c stands for ref + c
+    ca += acc;
+    cs2 += 2ll * (long long)q + (long long)acc + 2ll * (long long)ref * acc;
+    // the block's sums are final: commit them before the stores, which
+    // other workgroups then overlap
+    if (commit_here) commit_sweep<NT>(d, b, ca, cs2, t);
 
     // ---- store the block: aligned 16-byte chunks (LDS and global columns
     // share their alignment), masked single stores in the partial chunks
@@ -656,7 +734,59 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
             }
         }
     }
-    block_commit<NT>(d, b, acc, q, (long long)ref);
+    return true;
+}
+
+// The SX x SY sub-blocks (shape TX x TY each) of block (bx, by) with wide
+// staging.
+template <int D, int TX, int TY, int NT, typename E, int SCHED, int SX, int SY>
+__device__ __forceinline__ void wide_sweep(E *lds, SurfDev &d, int bx, int by, long long t, int ox, int oy,
+                                           int *s_bad, long long &ca, long long &cs2, int b)
+{
+#pragma unroll 1
+    for (int j = 0; j < SY; ++j)
+#pragma unroll 1
+        for (int i = 0; i < SX; ++i) {
+            __syncthreads();  // the previous stores have read the LDS
+            region_sweep<D, TX, TY, NT, E, SCHED, 4>(lds, d, bx * SX + i, by * SY + j, t, ox, oy, s_bad, ca, cs2,
+                                                     i == SX - 1 && j == SY - 1, b);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// block_sweep: one sweep for every active surface of the descriptor table,
+// int32 heights in HBM; one workgroup per tile block, E the LDS element
+// type, EW the wider type for blocks whose range does not fit E (void: E
+// always fits).  The whole sweep, its exact sums included, is this one
+// launch.
+// ---------------------------------------------------------------------------
+template <int D, int TX, int TY, int NT, typename E, typename EW, int SCHED = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    WideOcc<D, TX, TY, NT, 4, (int)sizeof(E), WideSize<EW>::v>::v))) void block_sweep(SurfDev *__restrict__ descs, int nsurf,
+                                                  const int *__restrict__ owner, int xmode, int xnbx)
+{
+    using W = WideSplit<D, TX, TY, NT, 4, (int)sizeof(E), WideSize<EW>::v>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds_raw[W::BYTES];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+
+    const int lb = block_map(blockIdx.x, gridDim.x, xmode, xnbx);
+    SurfDev &d = descs[find_surface(descs, nsurf, owner, lb)];
+    const long long t = d.t;
+    if (t >= d.t_end) return;
+    const uint32_t s = (uint32_t)t;
+    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, d.key0, d.key1);
+    const int ox = (int)(org.v[0] % (2u * D));
+    const int oy = (int)(org.v[1] % (2u * D));
+    const int b = lb - d.block_start;
+    const int bx = b % d.nbx, by = b / d.nbx;
+    long long ca = 0, cs2 = 0;
+    __syncthreads();  // s_bad cleared
+    if (__builtin_expect(!region_sweep<D, TX, TY, NT, E, SCHED>((E *)lds_raw, d, bx, by, t, ox, oy, &s_bad, ca, cs2,
+                                                                 true, b), 0)) {
+        if constexpr (!std::is_void<EW>::value)
+            wide_sweep<D, TX / W::SX, TY / W::SY, NT, EW, SCHED, W::SX, W::SY>((EW *)lds_raw, d, bx, by, t, ox, oy,
+                                                                           &s_bad, ca, cs2, b);
     }
 }
 
@@ -667,8 +797,8 @@ __global__ __launch_bounds__(NT) void block_sweep(const SurfDev *__restrict__ de
 // sweep, so while N L <= 32766 every height of a sweep lies within 2^15 of
 // m0 = floor(S1 / L^2) at the sweep's start: h = m0 + int16(r - m0 mod 2^16)
 // recovers it from its residue r, and the difference of any two heights is
-// the int16 difference of their residues.  reduce_acc keeps m0 in the
-// accumulator area.
+// the int16 difference of their residues.  The sweep's last block keeps m0
+// in the accumulator area.
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(1))) uint16_t gu16;
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -734,44 +864,23 @@ template <> struct Stage16<int16_t> {
     }
 };
 
-// block_sweep16: block_sweep on 16-bit residues.  E = uint8 (checked; the
-// blocks that do not fit are queued) or int16 (FALLBACK: walks the queue).
-// Host requirements as for block_sweep, with chunks of 8 cells: L % 8 == 0,
-// RWL <= L, N L <= 32766, N D <= 96, and N (RW + RH + 4) + D^2 <= 32767 for
-// the int16 fallback.
-template <int D, int TX, int TY, int NT, typename E, bool FALLBACK, int SCHED = 0>
-__global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ descs, int nsurf,
-                                                    const int *__restrict__ owner, int *__restrict__ queue)
+// region_sweep on 16-bit residues: E = uint8 (range-checked; returns false
+// when the region does not fit) or int16.  Host requirements as for
+// region_sweep, with chunks of 8 cells: L % 8 == 0, RWL <= L, N L <= 32766,
+// N D <= 96, and N (RW + RH + 4) + D^2 <= 32767 for int16.
+template <int D, int TX, int TY, int NT, typename E, int SCHED, int U = 8>
+__device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int by, long long t, int ox, int oy,
+                                               int *s_bad, long long &ca, long long &cs2, bool commit_here, int b)
 {
+    const uint32_t s = (uint32_t)t;
     using G = BlockGeom<D, TX, TY, 8>;
     using S = Stage16<E>;
     constexpr bool checked = sizeof(E) == 1;
-    __shared__ __attribute__((aligned(16))) E lds[G::RWL * G::RH];
-    __shared__ int s_bad;
-
-    if (checked) {
-        if (threadIdx.x == 0) s_bad = 0;
-        __syncthreads();
-    }
-    const int nq = FALLBACK ? queue[0] : 1;
-    for (int item = FALLBACK ? (int)blockIdx.x : 0; item < nq; item += FALLBACK ? (int)gridDim.x : 1) {
-    const int lb = FALLBACK ? queue[1 + item] : xcd_remap(blockIdx.x, gridDim.x);
-    const SurfDev &d = descs[find_surface(descs, nsurf, owner, lb)];
-    const long long t = d.t;
-    if (t >= d.t_end) continue;
-
     const int L = d.L, N = d.N, T = d.T;
-    const uint32_t s = (uint32_t)t;
     const uint32_t k0 = d.key0, k1 = d.key1;
-    const gu16 *__restrict__ hin = (const gu16 *)d.buf[t & 1];
-    gu16 *__restrict__ hout = (gu16 *)d.buf[(t + 1) & 1];
+    const gu16 *__restrict__ hin = (const gu16 *)d.buf[s & 1u];
+    gu16 *__restrict__ hout = (gu16 *)d.buf[(s + 1u) & 1u];
 
-    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, k0, k1);
-    const int ox = (int)(org.v[0] % (2u * D));
-    const int oy = (int)(org.v[1] % (2u * D));
-
-    const int b = lb - d.block_start;
-    const int bx = b % d.nbx, by = b / d.nbx;
     int gx0 = ox + bx * TX * D - G::RING;
     int gy0 = oy + by * TY * D - G::RING;
     if (gx0 < 0) gx0 += L;
@@ -785,7 +894,6 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
     uint32_t umax = 0;
     {
         constexpr int NCH = G::CH * G::RH;
-        constexpr int U = 8;
         constexpr int FULL = NCH / (NT * U);
         auto fetch = [&](int i) {
             const int r = i / G::CH, cc = i - r * G::CH;
@@ -826,24 +934,29 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
         }
     }
     if (checked) {
-        // u = h - h_ref + 128 must lie in [0, 255 - N D] (see block_sweep);
+        // u = h - h_ref + 128 must lie in [0, 255 - N D] (see region_sweep);
         // |h - h_ref| < 2^15, so an out-of-range u shows as a 16-bit lane
         // above 255 - N D
-        if ((int)max(umax & 0xFFFFu, umax >> 16) > 255 - N * D) s_bad = 1;
+        if ((int)max(umax & 0xFFFFu, umax >> 16) > 255 - N * D) *s_bad = 1;
     }
     __syncthreads();
-    if (checked && s_bad) {
-        if (threadIdx.x == 0) {
-            const int k = atomicAdd(queue, 1);
-            queue[1 + k] = lb;
-        }
-        continue;
-    }
+    if (checked && *(volatile int *)s_bad) return false;
 
     const int off = G::RING + cpad;
     int acc = 0;
     int q = 0;
     sweep_phases<SCHED, D, TX, TY, NT, G::RWL, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    {
+        // true height of staged value 0: the reference site's height,
+        // recovered from m0 of the sweep's start, less the staging bias
+        // (read before the block is counted: the sweep's last block
+        // rewrites m0)
+        const long long m0 = *(const gi64 *)(d.acc + kMeanWord);
+        const long long base = m0 + (long long)(int16_t)(uint16_t)(ref_r - (uint32_t)m0) - S::bias;
+        ca += acc;
+        cs2 += 2ll * (long long)q + (long long)acc + 2ll * base * acc;
+    }
+    if (commit_here) commit_sweep<NT>(d, b, ca, cs2, t);
 
     // ---- store: 16-byte chunks of 8 residues; 16-bit stores in the partial
     // chunks at both ends of each row
@@ -902,39 +1015,51 @@ __global__ __launch_bounds__(NT) void block_sweep16(const SurfDev *__restrict__ 
             }
         }
     }
-    // true height of staged value 0
-    const long long m0 = *(const gi64 *)(d.acc + kMeanWord);
-    const long long href = m0 + (long long)(int16_t)(uint16_t)(ref_r - (uint32_t)m0);
-    block_commit<NT>(d, b, acc, q, href - S::bias);
-    }
+    return true;
 }
 
-// Folds each active surface's accumulated increments into its log (the
-// record of t+1 is the record of t plus the increments), clears them,
-// updates the floor of the mean height and advances t.  One 64-thread
-// workgroup per surface.
-__global__ __launch_bounds__(64) void reduce_acc(SurfDev *__restrict__ descs, int *__restrict__ queue)
+// int16 sub-blocks of a 16-bit storage block (see wide_sweep).
+template <int D, int TX, int TY, int NT, int SCHED, int SX, int SY>
+__device__ __forceinline__ void wide_sweep16(int16_t *lds, SurfDev &d, int bx, int by, long long t, int ox, int oy,
+                                             int *s_bad, long long &ca, long long &cs2, int b)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0;
-    SurfDev &d = descs[blockIdx.x];
+#pragma unroll 1
+    for (int j = 0; j < SY; ++j)
+#pragma unroll 1
+        for (int i = 0; i < SX; ++i) {
+            __syncthreads();  // the previous stores have read the LDS
+            region_sweep16<D, TX, TY, NT, int16_t, SCHED, 4>(lds, d, bx * SX + i, by * SY + j, t, ox, oy, s_bad, ca,
+                                                             cs2, i == SX - 1 && j == SY - 1, b);
+        }
+}
+
+// block_sweep on 16-bit residues: uint8 staging, int16 for the blocks that
+// do not fit it.
+template <int D, int TX, int TY, int NT, int SCHED = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WideOcc<D, TX, TY, NT, 8, 1, 2>::v))) void block_sweep16(SurfDev *__restrict__ descs, int nsurf,
+                                                    const int *__restrict__ owner, int xmode, int xnbx)
+{
+    using W = WideSplit<D, TX, TY, NT, 8, 1, 2>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds_raw[W::BYTES];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+
+    const int lb = block_map(blockIdx.x, gridDim.x, xmode, xnbx);
+    SurfDev &d = descs[find_surface(descs, nsurf, owner, lb)];
     const long long t = d.t;
     if (t >= d.t_end) return;
-    long long *a = d.acc + 3 * threadIdx.x;
-    long long x = a[0], y = a[1], z = a[2];
-    a[0] = 0;
-    a[1] = 0;
-    a[2] = 0;
-    wave_reduce3(x, y, z);
-    if (threadIdx.x == 0) {
-        const long long *prev = d.log + 3 * (t % d.log_cap);
-        long long *e = d.log + 3 * ((t + 1) % d.log_cap);
-        const long long s1 = prev[0] + x, s2 = prev[1] + y;
-        e[0] = s1;
-        e[1] = s2;
-        e[2] = z;
-        d.acc[kMeanWord] = s1 / ((long long)d.L * d.L);
-        d.t = t + 1;
-    }
+    const uint32_t s = (uint32_t)t;
+    const u32x4 org = philox4x32_10(0u, 0u, s, 2u, d.key0, d.key1);
+    const int ox = (int)(org.v[0] % (2u * D));
+    const int oy = (int)(org.v[1] % (2u * D));
+    const int b = lb - d.block_start;
+    const int bx = b % d.nbx, by = b / d.nbx;
+    long long ca = 0, cs2 = 0;
+    __syncthreads();  // s_bad cleared
+    if (__builtin_expect(!region_sweep16<D, TX, TY, NT, uint8_t, SCHED>(lds_raw, d, bx, by, t, ox, oy, &s_bad, ca,
+                                                                         cs2, true, b), 0))
+        wide_sweep16<D, TX / W::SX, TY / W::SY, NT, SCHED, W::SX, W::SY>((int16_t *)lds_raw, d, bx, by, t, ox, oy,
+                                                                     &s_bad, ca, cs2, b);
 }
 
 // Conversions between int32 heights and 16-bit residues (grid-stride).

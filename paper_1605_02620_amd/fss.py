@@ -2,7 +2,7 @@
 
 Ensembles of surfaces of sizes L = 32..512 run in one batch to the steady
 state; W is averaged over t >= t_start and over realizations; the direct fit
-W_sat ~ L^alpha (Eq. (9)) and the effective exponents of Eq. (8) follow, and
+W_sat ~ L^alpha (Eq. (12)) and the effective exponents of Eq. (8) follow, and
 the shape of the width and height distributions (Eqs. (13)-(15)) is measured
 in the same window.
 

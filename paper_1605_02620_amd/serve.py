@@ -22,7 +22,7 @@ KEEP_HEIGHTS = 1
 
 class Engine:
     def __init__(self, pool_bytes: int, max_running: int = 256, D: int = 8, device="cuda",
-                 stream=None):
+                 stream=None, tune: bool = False):
         dev = _require_gpu(device)
         self.D = int(D)
         self.stream = stream if stream is not None else torch.cuda.Stream(dev)
@@ -31,6 +31,9 @@ class Engine:
         check(lib().rsos_engine_create(ctypes.byref(self._h), ctypes.c_void_p(self.pool.data_ptr()),
                                        self.pool.numel() * 4, int(max_running), self.D,
                                        _stream_handle(self.stream)))
+        if tune:
+            # per-class autotuned launch configurations (results unchanged)
+            check(lib().rsos_engine_tune(self._h, 1))
         self._nsamples = {}
 
     def submit(self, L, N, seed, t_max, sample_t=(), keep_heights=False) -> int:

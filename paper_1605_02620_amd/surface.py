@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Moments, Params, Width, check, lib
+from ._lib import Moments, Params, Tune, Width, check, lib
 
 LOG_DTYPE = np.dtype([("t", np.int64), ("s1", np.int64), ("s2", np.int64),
                       ("accepted", np.int64), ("w2", np.float64)])
@@ -32,10 +32,10 @@ def _stream_handle(stream):
 SCHEDULES = {"checkerboard": 0, "double": _lib.FLAG_DT4}
 
 
-def _params(L, N, D, seed, packed=False, schedule="checkerboard"):
+def _params(L, N, D, seed, packed=False, schedule="checkerboard", tune=False):
     if schedule not in SCHEDULES:
         raise ValueError(f"schedule must be one of {sorted(SCHEDULES)}")
-    flags = (_lib.FLAG_PACKED16 if packed else 0) | SCHEDULES[schedule]
+    flags = (_lib.FLAG_PACKED16 if packed else 0) | SCHEDULES[schedule] | (_lib.FLAG_TUNE if tune else 0)
     return Params(int(L), int(N), int(D), flags, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)).value)
 
 
@@ -53,11 +53,14 @@ class Surface:
     the int32 readout scratch.
 
     schedule="double" runs the paper's double-tiling schedule (RSOS_FLAG_DT4)
-    instead of the tile checkerboard."""
+    instead of the tile checkerboard.
+
+    tune=True takes the launch configuration from the autotuner
+    (RSOS_FLAG_TUNE; tuned on first use of the key): same results."""
 
     def __init__(self, L: int, N: int = 1, seed: int = 0, D: int = 8, h0=None, t0: int = 0,
                  log_cap: int = 0, device="cuda", stream=None, packed: bool = False,
-                 schedule: str = "checkerboard"):
+                 schedule: str = "checkerboard", tune: bool = False):
         dev = _require_gpu(device)
         self.L, self.N, self.D, self.seed = int(L), int(N), int(D), int(seed)
         self.packed = bool(packed)
@@ -67,7 +70,7 @@ class Surface:
         self.bufs = (torch.empty(n, dtype=torch.int32, device=dev),
                      torch.empty(n, dtype=torch.int32, device=dev))
         self.schedule = schedule
-        p = _params(L, N, D, seed, self.packed, schedule)
+        p = _params(L, N, D, seed, self.packed, schedule, tune)
         h0p = None
         if h0 is not None:
             self._h0 = np.ascontiguousarray(np.asarray(h0, dtype=np.int32).reshape(-1))
@@ -155,7 +158,7 @@ class Batch:
     ALIGN = 64  # elements (256 bytes) between surfaces in the pool
 
     def __init__(self, specs, D: int = 8, log_cap: int = 0, device="cuda", stream=None,
-                 packed: bool = False, schedule: str = "checkerboard"):
+                 packed: bool = False, schedule: str = "checkerboard", tune: bool = False):
         dev = _require_gpu(device)
         self.specs = [(int(L), int(N), int(seed)) for (L, N, seed) in specs]
         self.D = int(D)
@@ -169,7 +172,7 @@ class Batch:
         self.pool = torch.empty(max(off, 1), dtype=torch.int32, device=dev)
         self.work = torch.empty(max(off, 1), dtype=torch.int32, device=dev)
         self.schedule = schedule
-        ps = (Params * len(self.specs))(*[_params(L, N, D, s, self.packed, schedule)
+        ps = (Params * len(self.specs))(*[_params(L, N, D, s, self.packed, schedule, tune)
                                           for (L, N, s) in self.specs])
         self._h = ctypes.c_void_p()
         check(lib().rsos_batch_init(ctypes.byref(self._h), len(self.specs), ps,
@@ -278,6 +281,48 @@ class MultiSurface:
             pass
 
 
+def tune(L: int, N: int = 1, D: int = 8, batch: bool = False, packed: bool = False,
+         schedule: str = "checkerboard") -> dict:
+    """The autotuner's configuration for the key (L, N, D, storage,
+    schedule, alone or batched), tuning it on first use (rsos_tune)."""
+    p = _params(L, N, D, 0, packed, schedule)
+    t = Tune()
+    check(lib().rsos_tune(ctypes.byref(p), int(bool(batch)), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def tune_candidates(L: int, N: int = 1, D: int = 8, batch: bool = False, packed: bool = False,
+                    schedule: str = "checkerboard") -> list:
+    """Every launch configuration the autotuner considers for the key."""
+    p = _params(L, N, D, 0, packed, schedule)
+    n = ctypes.c_int32()
+    check(lib().rsos_tune_candidates(ctypes.byref(p), int(bool(batch)), None, 0, ctypes.byref(n)))
+    buf = (Tune * max(n.value, 1))()
+    check(lib().rsos_tune_candidates(ctypes.byref(p), int(bool(batch)), buf, n.value, ctypes.byref(n)))
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+def tune_set(L: int, N: int, D: int, choice: dict, batch: bool = False, packed: bool = False,
+             schedule: str = "checkerboard"):
+    """Enters a configuration for the key without timing it (rsos_tune_set)."""
+    p = _params(L, N, D, 0, packed, schedule)
+    t = Tune(**{k: choice[k] for k in ("TX", "TY", "NT", "elem", "xmode")},
+             graph_sweeps=int(choice.get("graph_sweeps") or 32))
+    check(lib().rsos_tune_set(ctypes.byref(p), int(bool(batch)), ctypes.byref(t)))
+
+
+def tune_clear():
+    check(lib().rsos_tune_clear())
+
+
+def tune_save(path: str):
+    check(lib().rsos_tune_save(str(path).encode()))
+
+
+def tune_load(path: str):
+    check(lib().rsos_tune_load(str(path).encode()))
+
+
 def philox(ctr, key):
     """The library's own Philox4x32-10 block function, run on the host."""
     c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
@@ -291,4 +336,5 @@ def w2(L, s1, s2):
     return float(lib().rsos_w2(int(L), int(s1), int(s2)))
 
 
-__all__ = ["Surface", "Batch", "MultiSurface", "philox", "w2", "LOG_DTYPE", "_lib"]
+__all__ = ["Surface", "Batch", "MultiSurface", "philox", "w2", "tune", "tune_candidates", "tune_set",
+           "tune_clear", "tune_save", "tune_load", "LOG_DTYPE", "_lib"]

@@ -103,8 +103,8 @@ def test_parameter_checks_without_gpu(so):
         st = lib.rsos_init(ctypes.byref(h), ctypes.byref(p), None, None, None, 0, 0, None)
         return st, lib.rsos_last_error().decode()
 
-    assert init(1024, 1, 8, 4)[0] == _lib.E_INVAL
-    assert "flags" in init(1024, 1, 8, 4)[1]
+    assert init(1024, 1, 8, 8)[0] == _lib.E_INVAL
+    assert "flags" in init(1024, 1, 8, 8)[1]
     st, msg = init(1024, 1, 4, _lib.FLAG_DT4)                # double tiling: D = 8 or 16
     assert st == _lib.E_INVAL and "double tiling" in msg
     st, msg = init(1024, 1, 8, _lib.FLAG_DT4 | _lib.FLAG_PACKED16)

@@ -62,7 +62,7 @@ def test_dt_matches_oracle(rsos, oracle, L, N, D, seed, sweeps, start):
     h0 = workloads.flat(L) if start == "flat" else workloads.rough(L, min(N, 4), seed=seed)
     s = rsos.Surface(L, N=N, seed=seed, D=D, h0=None if start == "flat" else h0, schedule="double")
     if L > 128:
-        assert s.kernel_name().endswith(",dt>")
+        assert s.kernel_name().endswith(",1>")
     s.sweep(sweeps)
     r_h, r_log = _oracle_dt(oracle, h0, L, N, D, seed, 0, sweeps)
     _compare(s.log(1, sweeps), r_log, s.heights(), r_h)

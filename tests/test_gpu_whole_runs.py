@@ -1,0 +1,138 @@
+"""Whole-run GPU parity against expected values that the CPU oracle wrote
+(tests/golden/make_whole_runs.py, which calls only oracle/): every sweep's
+(S1, S2, A) of Eq. (2) and the SHA-256 of the final heights, for the
+growth runs of Sec. II / III.A at the workloads' full lengths, run the way
+the benchmark runs them (non-default stream, hipGraph replays).
+
+  single_L16384      L = 16384, N = 1, 2000 sweeps
+  step_L8192_N*      L = 8192, N = 1, 2, 4, 5000 sweeps each
+  ensemble_L*        the first surface of each size of the 256-surface
+                     ensemble, 10^4 sweeps, run inside the whole ensemble
+  served_subset      the served stream's jobs with L^2 t_max <= 2^29 plus a
+                     seeded sample of larger ones, served together
+
+A run whose expected values have not been generated yet is skipped with
+that reason.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "whole_runs")
+
+
+def _say(msg):
+    print(f"[whole-run] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rsos():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1605_02620_amd as pkg
+    return pkg
+
+
+def _gold(name):
+    meta = os.path.join(GOLD, name + ".json")
+    if not os.path.exists(meta):
+        pytest.skip(f"{name}: expected values not generated (tests/golden/make_whole_runs.py {name})")
+    return json.load(open(meta)), np.load(os.path.join(GOLD, name + ".npz"))
+
+
+def _sha(h):
+    return hashlib.sha256(np.ascontiguousarray(h, dtype="<i4").tobytes()).hexdigest()
+
+
+def _check_log(lg, z, what):
+    for name, key in (("s1", "s1"), ("s2", "s2"), ("accepted", "a")):
+        bad = np.nonzero(lg[name] != z[key])[0]
+        assert bad.size == 0, f"{what}: {name} differs first at t={int(bad[0]) + 1}"
+
+
+def _single(rsos, name, packed=False):
+    import torch
+    meta, z = _gold(name)
+    L, N, D, seed, n = meta["L"], meta["N"], meta["D"], meta["seed"], meta["sweeps"]
+    _say(f"{name}: L={L} N={N} D={D} seed={seed} sweeps={n} packed={packed}")
+    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=n + 1, stream=torch.cuda.Stream(), packed=packed)
+    s.sweep(n)
+    lg = s.log(1, n)
+    _check_log(lg, z, name)
+    assert _sha(s.heights()) == meta["final_heights_sha256"], f"{name}: final heights differ"
+    s.close()
+
+
+def test_single_surface_whole_run(rsos):
+    _single(rsos, "single_L16384")
+
+
+def test_single_surface_whole_run_16bit_storage(rsos):
+    _single(rsos, "single_L16384", packed=True)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_step_heights_whole_run(rsos, N):
+    _single(rsos, f"step_L8192_N{N}")
+
+
+def test_ensemble_whole_run(rsos):
+    """The whole 256-surface ensemble in one batch for 10^4 sweeps; the
+    first surface of each size is compared sweep by sweep."""
+    import torch
+    ens = workloads.cfg_ensemble()
+    names = {}
+    for i, s in enumerate(ens):
+        if s.L not in names:
+            names[s.L] = i
+    golds = {L: _gold(f"ensemble_L{L}") for L in names}
+    n = ens[0].sweeps
+    _say(f"ensemble: {len(ens)} surfaces, {n} sweeps")
+    b = rsos.Batch([(s.L, s.N, s.seed) for s in ens], D=8, log_cap=n + 1, stream=torch.cuda.Stream())
+    b.sweep(n)
+    for L, i in names.items():
+        meta, z = golds[L]
+        assert (ens[i].seed, ens[i].N, n) == (meta["seed"], meta["N"], meta["sweeps"])
+        _check_log(b.log(i, 1, n), z, f"ensemble surface {i} (L={L})")
+        assert _sha(b.heights(i)) == meta["final_heights_sha256"], f"ensemble surface {i}: heights differ"
+    b.close()
+
+
+def test_served_subset_whole_runs(rsos):
+    """The subset's jobs served together through the continuous-batching
+    engine (all submitted at once; admission by footprint), each compared
+    at its sample times and on its final heights."""
+    from paper_1605_02620_amd import serve
+    meta, z = _gold("served_subset")
+    jobs = {j.job_id: j for j in workloads.job_stream(n_jobs=meta["stream"]["n_jobs"], rate_per_s=1.0,
+                                                      seed=meta["stream"]["seed"])}
+    ids = [int(i) for i in z["job_id"]]
+    off = z["offsets"]
+    _say(f"served subset: {len(ids)} jobs")
+    eng = serve.Engine(pool_bytes=8 << 30, max_running=256, D=8)
+    handle = {}
+    for k, jid in enumerate(ids):
+        j = jobs[jid]
+        t = z["t"][off[k]:off[k + 1]]
+        assert list(t) == workloads.pow2_grid(j.t_max)
+        handle[jid] = eng.submit(j.L, j.N, j.seed, j.t_max, sample_t=t, keep_heights=True)
+    while eng.stats()["running"] or eng.stats()["queued"]:
+        eng.step(1 << 20)
+    for k, jid in enumerate(ids):
+        j = jobs[jid]
+        samples, h, _ = eng.result(handle[jid], heights=True)
+        sl = slice(off[k], off[k + 1])
+        for name, key in (("s1", "s1"), ("s2", "s2"), ("accepted", "a")):
+            assert np.array_equal(samples[name], z[key][sl]), f"job {jid} (L={j.L}, N={j.N}): {name} differs"
+        assert _sha(h) == meta["final_heights_sha256"][str(jid)], f"job {jid}: final heights differ"
+        eng.release(handle[jid])
+    eng.close()

@@ -33,8 +33,8 @@ def test_traffic_summary_scaling(tmp_path):
     the probe's five 1 GiB copies; the largest block_sweep instance is the
     dominant one."""
     from paper_1605_02620_amd import profiling
-    main = "void rsosk::block_sweep<8, 32, 8, 256, signed char, false, 0>(args)"
-    fb = "void rsosk::block_sweep<8, 32, 8, 256, short, true, 0>(args)"
+    main = "void rsosk::block_sweep<8, 32, 8, 256, signed char, short, 0>(args)"
+    fb = "void rsosk::block_sweep<8, 32, 8, 256, short, void, 0>(args)"
     copy = "__amd_rocclr_copyBuffer"
     gib_kib = float(1 << 20)
     # FETCH reads half the copy's bytes (scale 2), WRITE all of them (scale 1)
@@ -61,23 +61,24 @@ def test_traffic_lookup_matches_instance(monkeypatch):
 
     monkeypatch.setattr(profiling, "current_traffic", fake)
     stored["block_sweep_traffic.json"] = {
-        "kernel": "void rsosk::block_sweep<8, 32, 8, 256, signed char, false, 0>(rsosk::SurfDev const*)",
+        "kernel": "void rsosk::block_sweep<8, 32, 8, 256, signed char, short, 0>(rsosk::SurfDev*, int, int const*, int, int)",
         "traffic_bytes_per_launch": 11}
     stored["block_sweep16_traffic.json"] = {
-        "kernel": "void rsosk::block_sweep16<8, 32, 8, 256, unsigned char, false, 0>(rsosk::SurfDev const*)",
+        "kernel": "void rsosk::block_sweep16<8, 32, 8, 256, 0>(rsosk::SurfDev*, int, int const*, int, int)",
         "traffic_bytes_per_launch": 22}
     stored["block_sweep_dt_traffic.json"] = {
-        "kernel": "void rsosk::block_sweep<8, 32, 8, 256, signed char, false, 1>(rsosk::SurfDev const*)",
+        "kernel": "void rsosk::block_sweep<8, 32, 8, 256, signed char, short, 1>(rsosk::SurfDev*, int, int const*, int, int)",
         "traffic_bytes_per_launch": 33}
-    assert bench._traffic("block_sweep<8,32,8,256,int8>", False) == 11
-    assert bench._traffic("block_sweep16<8,32,8,256,uint8>", True) == 22
-    assert bench._traffic("block_sweep<8,32,8,256,int8,dt>", False, "double") == 33
+    assert bench.kernel_instance(stored["block_sweep_traffic.json"]["kernel"]) == "block_sweep<8,32,8,256,int8,int16,0>"
+    assert bench._traffic("block_sweep<8,32,8,256,int8,int16,0>", False) == 11
+    assert bench._traffic("block_sweep16<8,32,8,256,0>", True) == 22
+    assert bench._traffic("block_sweep<8,32,8,256,int8,int16,1>", False, "double") == 33
     # another shape, staging type or schedule is never reported
-    assert bench._traffic("block_sweep<8,32,8,192,int8>", False) is None
-    assert bench._traffic("block_sweep<8,32,8,256,int16>", False) is None
-    assert bench._traffic("block_sweep<8,32,8,256,int8>", False, "double") is None
+    assert bench._traffic("block_sweep<8,32,8,192,int8,int16,0>", False) is None
+    assert bench._traffic("block_sweep<8,32,8,256,int16,void,0>", False) is None
+    assert bench._traffic("block_sweep<8,32,8,256,int8,int16,0>", False, "double") is None
     stored["block_sweep_traffic.json"]["kernel"] = stored["block_sweep_dt_traffic.json"]["kernel"]
-    assert bench._traffic("block_sweep<8,32,8,256,int8>", False) is None
+    assert bench._traffic("block_sweep<8,32,8,256,int8,int16,0>", False) is None
 
 
 def test_committed_summaries_describe_current_source():
