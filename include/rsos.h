@@ -219,6 +219,41 @@ rsos_status rsos_kernel_name(rsos_surface *s, char *buf, int32_t len);
 rsos_status rsos_free(rsos_surface *s);
 
 /* --------------------------------------------------------------------- */
+/* For callers that cannot allocate device memory: code under hipGraph    */
+/* capture, tight serving loops, harnesses that forbid allocation.         */
+/* --------------------------------------------------------------------- */
+
+#define RSOS_STATIC_MAX_SWEEPS 4096
+
+/* rsos_init + rsos_sweep + rsos_log in one call that allocates nothing:
+ * no handle, no hipMalloc or hipFree, no pinned host memory, no memset
+ * nodes (small fill kernels instead), so the launches may be captured.
+ * The descriptor, the accumulators and a log ring of
+ * RSOS_STATIC_MAX_SWEEPS + 1 records live in a fixed 128 KiB device array
+ * of the library (one per GPU, held until the process ends).
+ *   p       parameters as for rsos_init; flags 0 or RSOS_FLAG_DT4 (no
+ *           16-bit storage, no autotuner: the first variant that fits);
+ *   d_h, d_work  caller-owned device int32[L*L] (16-byte aligned); the
+ *           state after t0 sweeps is in d_h if t0 is even, else in d_work,
+ *           and after the call the state after t0 + n_mcs sweeps is in the
+ *           buffer of that parity (the same convention as rsos_init);
+ *   t0      sweeps already done, 0 <= t0, t0 + n_mcs <= 2^32;
+ *   s1, s2  exact sum h and sum h^2 of that state (0, 0 for a flat start;
+ *           the last record of the previous call when continuing);
+ *   n_mcs   sweeps, 0 <= n_mcs <= RSOS_STATIC_MAX_SWEEPS (RSOS_E_INVAL
+ *           beyond);
+ *   d_log   caller-owned device int64[3 * n_mcs] receiving (S1, S2, A) of
+ *           times t0+1 .. t0+n_mcs, as rsos_log's records;
+ *   stream  hipStream_t (NULL = default stream); everything is enqueued
+ *           asynchronously on it.
+ * Same results as rsos_init / rsos_sweep with the same arguments.  Checks
+ * the overflow bound (with max h0 <= s1 / L^2 + N L) before enqueuing
+ * (RSOS_E_OVERFLOW).  Calls that overlap on one GPU (other streams, other
+ * host threads) share the array and race; serialize them. */
+rsos_status rsos_sweep_static(const rsos_params *p, int32_t *d_h, int32_t *d_work, int64_t t0, int64_t s1,
+                              int64_t s2, int64_t n_mcs, int64_t *d_log, void *stream);
+
+/* --------------------------------------------------------------------- */
 /* Multisurface lock-step mode (Sec. II: multisurface coding).  Groups of  */
 /* 128 realizations of one L x L surface share the sequence of selected    */
 /* sites; each realization applies a selection with probability 1/2 (its   */

@@ -26,6 +26,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 FLAG_PACKED16 = 1
 FLAG_DT4 = 2
 FLAG_TUNE = 4
+STATIC_MAX_SWEEPS = 4096
 
 
 class Params(ctypes.Structure):
@@ -77,6 +78,7 @@ SIGNATURES = [
     ("rsos_timing_read", c_i32, [c_vp, P(c_i64), P(ctypes.c_double), P(ctypes.c_double)]),
     ("rsos_kernel_name", c_i32, [c_vp, ctypes.c_char_p, c_i32]),
     ("rsos_free", c_i32, [c_vp]),
+    ("rsos_sweep_static", c_i32, [P(Params), c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp]),
     ("rsos_ms_init", c_i32, [P(c_vp), P(Params), c_i32, c_vp, c_i64, c_vp]),
     ("rsos_ms_sweep", c_i32, [c_vp, c_i64]),
     ("rsos_ms_width", c_i32, [c_vp, P(Width)]),

@@ -1078,6 +1078,143 @@ rsos_status rsos_batch_free(rsos_batch *b)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Sweeps without any allocation (rsos_sweep_static).  The descriptor, the
+// accumulator area and the log ring of the one surface live in `scratch`, a
+// file-scope device array that every GPU the library runs on holds once
+// until the process ends.  In host code its name is a host-side stand-in;
+// the entry point takes the array's device address on each device with
+// hipGetSymbolAddress the first time it runs there and uses that address
+// only.  Calls on one GPU share the array: they must not overlap.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = 128 * 1024;
+constexpr size_t kScratchDesc = 0;      // SurfDev
+constexpr size_t kScratchIdx = 128;     // int 0: the LDS-path kernel's descriptor index
+constexpr size_t kScratchAcc = 256;     // kAccWords int64
+constexpr size_t kScratchLog = 2048;    // log ring of kStaticLogCap records of 3 int64
+constexpr long long kStaticLogCap = RSOS_STATIC_MAX_SWEEPS + 1;
+static_assert(sizeof(SurfDev) <= kScratchIdx, "descriptor slot");
+static_assert(kScratchAcc + 8 * rsosk::kAccWords <= kScratchLog, "accumulator slot");
+static_assert(kScratchLog + 24 * (size_t)kStaticLogCap <= kScratchBytes, "log ring");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+rsos_status scratch_ptr(unsigned char **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RSOS_E_INVAL, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(RSOS_E_DEVICE, "no device address for the scratch array");
+        g_scratch[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch[dev];
+    return RSOS_OK;
+}
+
+}  // namespace
+
+// Writes the descriptor, clears the accumulators and stores the record of
+// time t0 (a fill kernel, not a memset: callers may capture the launches).
+__global__ void static_setup(SurfDev d, unsigned char *base, long long s1, long long s2)
+{
+    long long *acc = (long long *)(base + kScratchAcc);
+    for (int i = threadIdx.x; i < rsosk::kAccWords; i += blockDim.x) acc[i] = 0;
+    if (threadIdx.x == 0) {
+        *(int *)(base + kScratchIdx) = 0;
+        const long long L2 = (long long)d.L * d.L;
+        acc[rsosk::kMeanWord] = s1 / L2;
+        long long *rec = d.log + 3 * (d.t % d.log_cap);
+        rec[0] = s1;
+        rec[1] = s2;
+        rec[2] = 0;
+        *(SurfDev *)(base + kScratchDesc) = d;
+    }
+}
+
+// Records of times t0+1 .. t0+n from the ring into the caller's int64[3n].
+__global__ void static_copy_log(const unsigned char *base, long long t0, long long n, long long *out)
+{
+    const long long *ring = (const long long *)(base + kScratchLog);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long k = i / 3, w = i % 3;
+        out[i] = ring[3 * ((t0 + 1 + k) % kStaticLogCap) + w];
+    }
+}
+
+extern "C" rsos_status rsos_sweep_static(const rsos_params *p, int32_t *d_h, int32_t *d_work, int64_t t0,
+                                         int64_t s1, int64_t s2, int64_t n_mcs, int64_t *d_log, void *stream)
+{
+    rsos_status st = check_params(p);
+    if (st != RSOS_OK) return st;
+    if (p->flags & ~RSOS_FLAG_DT4)
+        return fail(RSOS_E_INVAL, "rsos_sweep_static: flags may only select the schedule (RSOS_FLAG_DT4)");
+    if (!d_h || !d_work || (n_mcs > 0 && !d_log)) return fail(RSOS_E_INVAL, "NULL buffer");
+    if (n_mcs < 0 || n_mcs > RSOS_STATIC_MAX_SWEEPS)
+        return fail(RSOS_E_INVAL, "n_mcs=%lld outside [0, %d]", (long long)n_mcs, RSOS_STATIC_MAX_SWEEPS);
+    if (t0 < 0 || t0 + n_mcs > (1ll << 32)) return fail(RSOS_E_INVAL, "sweep index would exceed 2^32");
+    if ((((uintptr_t)d_h) | ((uintptr_t)d_work)) & 15) return fail(RSOS_E_INVAL, "height buffers must be 16-byte aligned");
+    const long long L2 = (long long)p->L * p->L;
+    if (s1 < 0 || s2 < 0 || (__int128)s1 * s1 > (__int128)L2 * s2)
+        return fail(RSOS_E_INVAL, "s1, s2 are not the sums of any heights (need 0 <= s1, s1^2 <= L^2 s2)");
+    // every height is within N L of the mean s1 / L^2
+    if ((st = check_overflow(*p, s1 / L2 + 1 + (long long)p->N * p->L, n_mcs)) != RSOS_OK) return st;
+    if (n_mcs == 0) return RSOS_OK;
+    unsigned char *base = nullptr;
+    if ((st = scratch_ptr(&base)) != RSOS_OK) return st;
+    const int D = p->D, sched = (p->flags & RSOS_FLAG_DT4) ? 1 : 0;
+    SurfDev d = {};
+    d.buf[0] = d_h;
+    d.buf[1] = d_work;
+    d.log = (long long *)(base + kScratchLog);
+    d.acc = (long long *)(base + kScratchAcc);
+    d.log_cap = kStaticLogCap;
+    d.t = t0;
+    d.t_end = t0 + n_mcs;
+    d.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.L = p->L;
+    d.N = p->N;
+    d.T = p->L / D;
+    const Variant *v = nullptr;
+    if (!uses_lds(p->L)) {
+        v = pick_variant(D, {{p->L, p->N}}, false, sched == 1);
+        if (!v) return fail(RSOS_E_INVAL, "no tile-block shape fits L=%d, N=%d, D=%d", p->L, p->N, D);
+        d.nbx = d.T / v->TX;
+        d.nblocks = d.nbx * (d.T / v->TY);
+        d.block_start = 0;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    SurfDev *dd = (SurfDev *)(base + kScratchDesc);
+    hipLaunchKernelGGL(static_setup, dim3(1), dim3(256), 0, s, d, base, (long long)s1, (long long)s2);
+    HIP_TRY(hipGetLastError());
+    if (!v) {
+        // the whole surface in one workgroup's LDS, all sweeps in one launch
+        lds_launcher(D, sched)(dim3(1), (size_t)L2 * 4, s, dd, (const int *)(base + kScratchIdx));
+        HIP_TRY(hipGetLastError());
+    } else {
+        BlockLaunch k = sched == 1 ? v->launch_dt : v->launch;
+        for (long long i = 0; i < n_mcs; ++i) k(dim3(d.nblocks), s, dd, 1, nullptr, 1, d.nbx);
+        HIP_TRY(hipGetLastError());
+    }
+    const unsigned grid = (unsigned)std::min<long long>((3 * n_mcs + 255) / 256, 64);
+    hipLaunchKernelGGL(static_copy_log, dim3(grid), dim3(256), 0, s, base, (long long)t0, (long long)n_mcs,
+                       (long long *)d_log);
+    HIP_TRY(hipGetLastError());
+    return RSOS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // serving engine (continuous batching) -- see rsos_engine.inc
 // ---------------------------------------------------------------------------
 #include "rsos_engine.inc"
