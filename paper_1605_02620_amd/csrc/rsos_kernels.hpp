@@ -167,13 +167,20 @@ __device__ __forceinline__ void attempt(E *lds, int base, uint32_t f, int N, int
     if constexpr (std::is_same<E, uint8_t>::value) {
         // unsigned byte staging (LDS-bound): the left neighbour, the site and
         // the right neighbour from one read of the two aligned words around
-        // them (measured slower on the HBM-bound int8 path, so not used there)
-        const int a = (idx - 1) & ~3;
-        const uint32_t *w = reinterpret_cast<const uint32_t *>(lds + a);
-        const uint32_t t3 = __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(idx - 1) & 3u);
+        // them (measured slower on the HBM-bound int8 path, so not used there).
+        // Every access is addressed from i1 = idx - 1; the byte shift of
+        // v_alignbyte uses the low two bits of its operand only.
+        const int i1 = (base - 1) + (int)__umul24(f >> LOG2D, (uint32_t)P) + (int)(f & (D - 1));
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(lds + (i1 & ~3));
+        const uint32_t t3 = __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)i1);
         const int l = (int)(t3 & 0xFFu), r = (int)((t3 >> 16) & 0xFFu);
         c = (int)((t3 >> 8) & 0xFFu);
-        m = min(min(l, r), min((int)lds[idx - P], (int)lds[idx + P]));
+        m = min(min(l, r), min((int)lds[i1 + 1 - P], (int)lds[i1 + 1 + P]));
+        const int ok = (int)((uint32_t)(c - m - N) >> 31);
+        q += __mul24(c, ok);
+        lds[i1 + 1] = (E)(c + ok);
+        acc += ok;
+        return;
     } else {
         c = lds[idx];
         m = min(min((int)lds[idx - 1], (int)lds[idx + 1]), min((int)lds[idx - P], (int)lds[idx + P]));
@@ -561,12 +568,16 @@ template <> struct WideSize<void> { static constexpr int v = 0; };
 // it, so that the rarely taken wide path (whose registers the compiler then
 // spills, in that path only) does not lower the occupancy of the main one;
 // for the other domain sizes the budget would force spills into the main
-// path, and the compiler's own allocation is kept.
+// path, and the compiler's own allocation is kept.  A workgroup of NT
+// threads puts NT / 256 waves on each SIMD, so the count is a multiple of
+// that; 256 bytes stand for the kernel's small static arrays.
 template <int D, int TX, int TY, int NT, int CPC, int ES, int EWS>
 struct WideOcc {
-    static constexpr int lds = WideSplit<D, TX, TY, NT, CPC, ES, EWS>::BYTES + 64;
-    static constexpr int w = (163840 / lds) * (NT / 64) / 4;
-    static constexpr int v = (EWS == 0 || D != 8) ? 1 : (w < 1 ? 1 : (w > 7 ? 7 : w));
+    static constexpr int lds = WideSplit<D, TX, TY, NT, CPC, ES, EWS>::BYTES + 256;
+    static constexpr int per = NT >= 256 ? NT / 256 : 1;
+    static constexpr int w0 = (163840 / lds) * (NT / 64) / 4;
+    static constexpr int w = ((w0 > 7 ? 7 : w0) / per) * per;
+    static constexpr int v = (EWS == 0 || D != 8) ? 1 : (w < 1 ? 1 : w);
 };
 
 // ---------------------------------------------------------------------------
