@@ -344,12 +344,16 @@ def bench_plain_jobs(jobs):
     attempts = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in jobs:
+    t_report = t0
+    for i, j in enumerate(jobs):
         s = rsos.Surface(j.L, N=j.N, seed=j.seed, D=8, log_cap=j.t_max + 1, stream=st, tune=True)
         s.sweep(j.t_max)
         s.log(1, j.t_max)  # the job's records (synchronises)
         s.close()
         attempts += j.L * j.L * j.t_max
+        if time.perf_counter() - t_report > 30.0:
+            t_report = time.perf_counter()
+            _progress(f"served: plain loop, {i + 1} of {len(jobs)} jobs")
     dt = time.perf_counter() - t0
     return attempts / (dt * 1e9), dt
 
@@ -375,7 +379,8 @@ def bench_served(jobs, rate_attempts_per_ns=None, load=0.9, pool_gib=8, tune=Tru
     timed = [workloads.Job(job_id=j.job_id, arrival_s=float(a), L=j.L, N=j.N, t_max=j.t_max, seed=j.seed)
              for j, a in zip(jobs, arr)]
     eng = serve.Engine(pool_bytes=pool_gib << 30, max_running=256, D=8, tune=tune)
-    res, summ = serve.serve(eng, timed, grid=lambda tm: workloads.pow2_grid(tm))
+    res, summ = serve.serve(eng, timed, grid=lambda tm: workloads.pow2_grid(tm),
+                            progress=lambda m: _progress(f"served: {m}"))
     eng.close()
     torch.cuda.synchronize()
     out = {"jobs_done": summ["jobs_done"], "wall_s": round(summ["wall_s"], 3),
@@ -387,12 +392,16 @@ def bench_served(jobs, rate_attempts_per_ns=None, load=0.9, pool_gib=8, tune=Tru
     return out
 
 
-def bench_serving(n_jobs):
+SERVED_LOADS = ("0.9", "0.9ff", "0.5")
+
+
+def bench_serving(n_jobs, loads=SERVED_LOADS):
     """Served against plain on the same jobs.  The autotuner's choices for
     every (L, N) class of the job set are made first (setup, outside every
     timed region).  capacity: all jobs arrive at once; then Poisson streams
     at 0.9 and 0.5 of that capacity (latency from arrival), and at 0.9 with
-    the untuned first-fit launch choice."""
+    the untuned first-fit launch choice ("0.9ff"), as many of them as
+    `loads` names."""
     from paper_1605_02620_amd import surface
     jobs = served_jobs(n_jobs)
     for (L, N) in sorted({(j.L, j.N) for j in jobs}):
@@ -412,10 +421,14 @@ def bench_serving(n_jobs):
     out["capacity"] = cap
     out["served_over_plain"] = round(cap["attempts_per_ns"] / plain_rate, 3)
     _progress(f"served: capacity {cap['attempts_per_ns']} attempts/ns")
-    out["at_0.9_load"] = bench_served(jobs, cap["attempts_per_ns"], 0.9)
-    _progress("served: 0.9 load done")
-    out["at_0.9_load_first_fit"] = bench_served(jobs, cap["attempts_per_ns"], 0.9, tune=False)
-    out["at_0.5_load"] = bench_served(jobs, cap["attempts_per_ns"], 0.5)
+    if "0.9" in loads:
+        out["at_0.9_load"] = bench_served(jobs, cap["attempts_per_ns"], 0.9)
+        _progress("served: 0.9 load done")
+    if "0.9ff" in loads:
+        out["at_0.9_load_first_fit"] = bench_served(jobs, cap["attempts_per_ns"], 0.9, tune=False)
+        _progress("served: 0.9 load, first fit, done")
+    if "0.5" in loads:
+        out["at_0.5_load"] = bench_served(jobs, cap["attempts_per_ns"], 0.5)
     return out
 
 
@@ -440,6 +453,9 @@ def main():
     ap.add_argument("--no-step", action="store_true", help="skip the step-height leg")
     ap.add_argument("--served-jobs", type=int, default=200,
                     help="jobs of the 2000-job served stream to serve (2000: the whole stream)")
+    ap.add_argument("--served-loads", default=",".join(SERVED_LOADS),
+                    help="comma-separated Poisson loads served after the capacity run: "
+                         "0.9, 0.9ff (0.9 with the untuned first-fit choice), 0.5")
     ap.add_argument("--no-tune", action="store_true", help="headline without the autotuner")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: read before the run if it exists, written after the "
@@ -519,7 +535,7 @@ def main():
         out["steady_state"] = bench_fss()
         _progress("steady state done")
     if not args.no_serve:
-        out["served"] = bench_serving(args.served_jobs)
+        out["served"] = bench_serving(args.served_jobs, tuple(x for x in args.served_loads.split(",") if x))
         _progress("served done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(L, N, D, seed)

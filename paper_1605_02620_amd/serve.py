@@ -91,18 +91,26 @@ class Engine:
 
 
 def serve(engine: Engine, jobs, chunk_ticks: int = 16, grid=None, keep_heights=False,
-          time_limit_s: float | None = None):
+          time_limit_s: float | None = None, progress=None, progress_every_s: float = 30.0):
     """Runs a stream of jobs (objects with job_id, arrival_s, L, N, t_max,
     seed) through the engine in real time.  grid(t_max) gives each job's
-    sample times.  Returns (per-job results dict, summary dict)."""
+    sample times; progress(message), if given, is called about every
+    progress_every_s seconds.  Returns (per-job results dict, summary
+    dict)."""
     order = sorted(jobs, key=lambda j: j.arrival_s)
     k = 0
     ids = {}
     delay = {}
     t0 = time.perf_counter()
     a0 = engine.stats()["attempts"]
+    t_report = t0
     while True:
         now = time.perf_counter() - t0
+        if progress is not None and time.perf_counter() - t_report > progress_every_s:
+            t_report = time.perf_counter()
+            st = engine.stats()
+            progress(f"{now:.0f} s: {k} of {len(order)} jobs submitted, {st['running']} running, "
+                     f"{st['queued']} queued")
         while k < len(order) and order[k].arrival_s <= now:
             j = order[k]
             gt = grid(j.t_max) if grid else [j.t_max]

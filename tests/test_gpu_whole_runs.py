@@ -60,11 +60,17 @@ def _check_log(lg, z, what):
 
 
 def _single(rsos, name, packed=False):
+    """One surface run whole in the benchmark's launch configuration (the
+    autotuner's choice for its key)."""
     import torch
     meta, z = _gold(name)
     L, N, D, seed, n = meta["L"], meta["N"], meta["D"], meta["seed"], meta["sweeps"]
     _say(f"{name}: L={L} N={N} D={D} seed={seed} sweeps={n} packed={packed}")
-    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=n + 1, stream=torch.cuda.Stream(), packed=packed)
+    s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=n + 1, stream=torch.cuda.Stream(), packed=packed,
+                     tune=True)
+    from paper_1605_02620_amd import surface
+    c = surface.tune(L, N, D, packed=packed)
+    _say(f"{name}: {c['TX']}x{c['TY']} tiles, {c['NT']} threads, xmode {c['xmode']}, graphs of {c['graph_sweeps']}")
     s.sweep(n)
     lg = s.log(1, n)
     _check_log(lg, z, name)
