@@ -98,17 +98,27 @@ __global__ __launch_bounds__(64) void ms_phase(const MsDev *__restrict__ dp, int
     const gu32 *lat = (const gu32 *)(d.lat + (size_t)g * L * L * 64) + 32 * hh;
     gu32 *latw = (gu32 *)(d.lat + (size_t)g * L * L * 64) + 32 * hh;
 
-    // ---- load the padded tile: 8 sites per instruction, 8 lanes x 16 B per site
-#pragma unroll 4
-    for (int i = 0; i < (P * P + 7) / 8; ++i) {
-        const int site = 8 * i + (lane >> 3);
-        if (site < P * P) {
+    // ---- load the padded tile: 8 sites per instruction, 8 lanes x 16 B per
+    // site; every load is issued before the first is used (the last pass's
+    // surplus lanes load the last site again and do not write it)
+    {
+        constexpr int NLD = (P * P + 7) / 8;
+        v4u vin[NLD];
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int site = min(8 * i + (lane >> 3), P * P - 1);
             const int sy = site / P, sx = site - sy * P;
             int gx = X0 + sx, gy = Y0 + sy;
             if (gx >= L) gx -= L;
             if (gy >= L) gy -= L;
-            const v4u v = *reinterpret_cast<const gv4u *>(lat + ((size_t)gy * L + gx) * 64 + 4 * (lane & 7));
-            *reinterpret_cast<uint4 *>(&lds[site * 64 + 8 * (lane & 7)]) = make_uint4(v.x, v.y, v.z, v.w);
+            vin[i] = *reinterpret_cast<const gv4u *>(lat + ((size_t)gy * L + gx) * 64 + 4 * (lane & 7));
+        }
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int site = 8 * i + (lane >> 3);
+            if (site < P * P)
+                *reinterpret_cast<uint4 *>(&lds[site * 64 + 8 * (lane & 7)]) =
+                    make_uint4(vin[i].x, vin[i].y, vin[i].z, vin[i].w);
         }
     }
     __syncthreads();
@@ -229,17 +239,28 @@ __global__ __launch_bounds__(128) void ms_phase_b(const MsDev *__restrict__ dp, 
     const uint32_t bias = 0x00800080u;
     const v4u sub = {pk_sub16(rv.x, bias), pk_sub16(rv.y, bias), pk_sub16(rv.z, bias), pk_sub16(rv.w, bias)};
 
-    // ---- load the padded tile: 8 sites per pass, 16 threads x 16 bytes per site
-#pragma unroll 4
-    for (int i = 0; i < (P * P + 7) / 8; ++i) {
-        const int site = 8 * i + (tid >> 4);
-        if (site < P * P) {
+    // ---- load the padded tile: 8 sites per pass, 16 threads x 16 bytes per
+    // site; every load is issued before the first is used (the last pass's
+    // surplus threads load the last site again and do not write it)
+    {
+        constexpr int NLD = (P * P + 7) / 8;
+        v4u vin[NLD];
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int site = min(8 * i + (tid >> 4), P * P - 1);
             const int sy = site / P, sx = site - sy * P;
-            const v4u v = *reinterpret_cast<const gv4u *>(lat + site_of(sy, sx) * 64 + 4 * ck);
-            const uint32_t w0 = pk_sub16(v.x, sub.x), w1 = pk_sub16(v.y, sub.y);
-            const uint32_t w2 = pk_sub16(v.z, sub.z), w3 = pk_sub16(v.w, sub.w);
-            *reinterpret_cast<uint2 *>(&lds[site * kMsReal + 8 * ck]) =
-                make_uint2(__builtin_amdgcn_perm(w1, w0, 0x06040200u), __builtin_amdgcn_perm(w3, w2, 0x06040200u));
+            vin[i] = *reinterpret_cast<const gv4u *>(lat + site_of(sy, sx) * 64 + 4 * ck);
+        }
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int site = 8 * i + (tid >> 4);
+            if (site < P * P) {
+                const v4u &v = vin[i];
+                const uint32_t w0 = pk_sub16(v.x, sub.x), w1 = pk_sub16(v.y, sub.y);
+                const uint32_t w2 = pk_sub16(v.z, sub.z), w3 = pk_sub16(v.w, sub.w);
+                *reinterpret_cast<uint2 *>(&lds[site * kMsReal + 8 * ck]) =
+                    make_uint2(__builtin_amdgcn_perm(w1, w0, 0x06040200u), __builtin_amdgcn_perm(w3, w2, 0x06040200u));
+            }
         }
     }
     __syncthreads();
