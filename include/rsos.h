@@ -171,7 +171,8 @@ rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, in
  * H = max(h0) + min(t + N L, D^2 t) < 2^31 and L^2 H^2 < 2^63 before
  * enqueuing anything (RSOS_E_OVERFLOW: no device work, t unchanged).  Each
  * sweep is one kernel launch (runs of them replayed as hipGraphs when the
- * surface has a stream); the exact sums of the sweep are part of it. */
+ * surface has a stream; the graph is captured by rsos_init, never inside
+ * rsos_sweep); the exact sums of the sweep are part of it. */
 rsos_status rsos_sweep(rsos_surface *s, int64_t n_mcs);
 
 /* Synchronises the stream and returns the record of the current time t:

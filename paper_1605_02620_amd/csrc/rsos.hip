@@ -514,6 +514,14 @@ struct SurfaceGroup {
         return RSOS_OK;
     }
 
+    // Captures the graph of graph_k sweeps when the group is created, so
+    // that no rsos_sweep call pays for a capture (surfaces on a stream).
+    rsos_status prepare_graph()
+    {
+        if (stream == nullptr || blk_idx.empty() || graph) return RSOS_OK;
+        return capture_graph(graph_k);
+    }
+
     rsos_status capture_graph(int k)
     {
         hipGraph_t g = nullptr;
@@ -816,6 +824,7 @@ rsos_status rsos_init(rsos_surface **out, const rsos_params *p, int32_t *d_h, in
     // initial state into the buffer of parity t0
     if ((st = g.load_initial(0, h0_host, s1)) != RSOS_OK) { g.destroy(); delete s; return st; }
     if ((st = g.init_record(0, s1, s2)) != RSOS_OK) { g.destroy(); delete s; return st; }
+    if ((st = mark(g, g.prepare_graph())) != RSOS_OK) { g.destroy(); delete s; return st; }
     *out = s;
     return RSOS_OK;
 }
@@ -1004,6 +1013,7 @@ rsos_status rsos_batch_init(rsos_batch **out, int32_t n, const rsos_params *p, i
             delete b;
             return st;
         }
+    if ((st = mark(g, g.prepare_graph())) != RSOS_OK) { g.destroy(); delete b; return st; }
     *out = b;
     return RSOS_OK;
 }
