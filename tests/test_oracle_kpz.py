@@ -24,22 +24,28 @@ def _beta(ts, w2, lo, hi):
 
 
 def test_growth_exponent_tiled_and_rs(oracle):
+    """W^2 ~ t^(2 beta) (Eq. (3)) in the growth regime: the tiled schedule
+    on L = 2048 over 64 <= t <= 1024 (mean of two seeds), random-sequential
+    updates on L = 1024 over 32 <= t <= 512."""
     oracle.set_threads(8)
     try:
-        L = 1024
-        h = workloads.flat(L)
-        lg = oracle.run(h, L, 1, 8, seed=3, t0=0, n=512)
-        b_tc = _beta(lg[:, 0], _w2(oracle, L, lg), 64, 512)
+        L = 2048
+        b = []
+        for seed in (3, 4):
+            h = workloads.flat(L)
+            lg = oracle.run(h, L, 1, 8, seed=seed, t0=0, n=1024)
+            b.append(_beta(lg[:, 0], _w2(oracle, L, lg), 64, 1024))
+        b_tc = float(np.mean(b))
     finally:
         oracle.set_threads(0)
-    assert 0.22 <= b_tc <= 0.26, b_tc
-    L = 512
+    assert 0.22 <= b_tc <= 0.26, b
+    L = 1024
     h = workloads.flat(L)
-    lg = oracle.rs_run(h, L, 1, rs_seed=3, t0=0, n=256)
-    b_rs = _beta(lg[:, 0], _w2(oracle, L, lg), 32, 256)
+    lg = oracle.rs_run(h, L, 1, rs_seed=3, t0=0, n=512)
+    b_rs = _beta(lg[:, 0], _w2(oracle, L, lg), 32, 512)
     assert 0.22 <= b_rs <= 0.26, b_rs
     # Sec. III.C: the domain decomposition must not change the exponents
-    assert abs(b_tc - b_rs) < 0.02, (b_tc, b_rs)
+    assert abs(b_tc - b_rs) < 0.02, (b, b_rs)
 
 
 def test_roughness_exponent_tiled(oracle):
@@ -60,4 +66,4 @@ def test_roughness_exponent_tiled(oracle):
             ws.append(_w2(oracle, L, lg[burn:]).mean())
         alphas.append(np.polyfit(np.log([32, 64, 128]), np.log(ws), 1)[0] / 2)
     a = float(np.mean(alphas))
-    assert 0.35 <= a <= 0.43, alphas
+    assert 0.36 <= a <= 0.42, alphas
