@@ -29,13 +29,14 @@
 namespace rsosk {
 
 constexpr int kMsReal = 128;    // realizations per group
-constexpr int kMsChunks = 256;  // most tile ranges summed in the first reduction step
+constexpr int kMsChunks = 64;   // most tile ranges summed per group
 
 struct MsDev {
     uint32_t *lat;        // [G][L*L] records of 128 16-bit residues (realization r at halfword r)
     long long *m0;        // [G][128] floor(S1 / L^2) of the current time
     int *part;            // [G][T*T][128]: 256 H + A of each tile's update in the current sweep
-    long long *chunk;     // [G][nchunk][128][2]: (A, H) summed over a range of tiles
+    long long *acc;       // [G][128][2]: (A, H) of the current sweep summed so far (zero between sweeps)
+    long long *done;      // [G][16]: ranges of tiles summed in the current sweep (word 0 of a 128-byte line)
     long long *log;       // [G][128][log_cap][3]: (S1, S2, A) of time tau at slot tau % log_cap
     long long *t;         // [G] sweeps done
     long long log_cap;
@@ -48,8 +49,9 @@ struct MsDev {
 // its accepted count (at most 2 D^2 = 128) and H the sum of h - m0 over its
 // accepted deposits (|h - m0| <= N L <= 32766, so |H| < 2^22 and the record
 // fits in 32 bits).  Plain stores, one per tile and realization: the sums
-// over tiles are formed by ms_partial and ms_reduce, not by device-scope
-// atomics on a few shared words (those serialised the whole phase).
+// over tiles are formed by ms_partial, which adds one sum per range of at
+// least 64 tiles and realization with a device-scope atomic (one such
+// addition per tile serialised the whole phase on a few words).
 __device__ __forceinline__ void ms_record(const MsDev &d, int g, uint32_t tile_id, int r, int A, int H)
 {
     d.part[((size_t)g * d.T * d.T + tile_id) * kMsReal + r] = H * 256 + A;
@@ -319,8 +321,8 @@ __global__ __launch_bounds__(128) void ms_phase_b(const MsDev *__restrict__ dp, 
     ms_record(d, g, tile_id, r, A, q + dref * A);
 }
 
-// The sums over tiles run in two steps, each a workgroup of kMsSub x 128
-// threads: thread (sub, r) adds every kMsSub-th value for realization r
+// The sums over a range of tiles: a workgroup of kMsSub x 128 threads,
+// thread (sub, r) adds every kMsSub-th value for realization r
 // (independent loads, unrolled, so the loads overlap), then the kMsSub
 // partial sums are combined in LDS.
 constexpr int kMsSub = 4;
@@ -341,14 +343,22 @@ __device__ __forceinline__ void ms_combine(long long &A, long long &H)
     }
 }
 
-// First step after both phases: workgroup (c, g) sums the tile records of
-// tile range c of group g for each of its 128 realizations.
+// After both phases: workgroup (c, g) sums the tile records of tile range c
+// of group g for each of its 128 realizations and adds the sums into the
+// group's accumulators; the workgroup that completes the group's count
+// folds them into each realization's log (a deposit on height h adds 2h + 1
+// to S2, and h = m0 + (h - m0)), updates floor(S1 / L^2), clears the
+// accumulators and advances the group's time.  Device-scope atomics without
+// fences, as for the block sweep: a workgroup counts itself only after its
+// additions have been performed, and the last one reads the accumulators
+// with device-scope atomic loads.
 __global__ __launch_bounds__(kMsSub * kMsReal) void ms_partial(const MsDev *__restrict__ dp)
 {
     const MsDev &d = *dp;
     const int c = blockIdx.x, g = blockIdx.y;
     const int sub = threadIdx.x / kMsReal, r = threadIdx.x % kMsReal;
-    if (d.t[g] >= d.t_end) return;
+    const long long t = d.t[g];
+    if (t >= d.t_end) return;
     const long long tiles = (long long)d.T * d.T;
     const long long cs = (tiles + d.nchunk - 1) / d.nchunk;
     const long long lo = c * cs, hi = min(tiles, lo + cs);
@@ -361,33 +371,28 @@ __global__ __launch_bounds__(kMsSub * kMsReal) void ms_partial(const MsDev *__re
         H += v >> 8;
     }
     ms_combine(A, H);
+    __shared__ int s_last;
+    typedef __attribute__((address_space(1))) unsigned long long gu64m;
+    gu64m *acc = (gu64m *)(d.acc + ((size_t)g * kMsReal + r) * 2);
     if (sub == 0) {
-        long long *o = d.chunk + (((size_t)g * d.nchunk + c) * kMsReal + r) * 2;
-        o[0] = A;
-        o[1] = H;
+        __hip_atomic_fetch_add(acc + 0, (unsigned long long)A, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(acc + 1, (unsigned long long)H, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the additions are performed before the workgroup is counted
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-}
-
-// Second step: folds each realization's sweep (A, H) into its log (a
-// deposit on height h adds 2h + 1 to S2, and h = m0 + (h - m0)), updates
-// floor(S1 / L^2) and advances the group's time.  One workgroup per group.
-__global__ __launch_bounds__(kMsSub * kMsReal) void ms_reduce(const MsDev *__restrict__ dp)
-{
-    const MsDev &d = *dp;
-    const int g = blockIdx.x;
-    const int sub = threadIdx.x / kMsReal, r = threadIdx.x % kMsReal;
-    const long long t = d.t[g];
-    if (t >= d.t_end) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long prev = __hip_atomic_fetch_add((gu64m *)(d.done + 16 * (size_t)g), 1ull,
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev + 1 == (unsigned long long)d.nchunk;
+    }
+    __syncthreads();
+    if (!s_last || sub != 0) return;
+    A = (long long)__hip_atomic_load(acc + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    H = (long long)__hip_atomic_load(acc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(acc + 0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(acc + 1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const size_t id = (size_t)g * kMsReal + r;
-    long long A = 0, H = 0;
-#pragma unroll 16
-    for (int c = sub; c < d.nchunk; c += kMsSub) {
-        const long long *o = d.chunk + (((size_t)g * d.nchunk + c) * kMsReal + r) * 2;
-        A += o[0];
-        H += o[1];
-    }
-    ms_combine(A, H);
-    if (sub != 0) return;
     const long long S2 = 2 * (d.m0[id] * A + H) + A;
     const long long *prev = d.log + (id * d.log_cap + t % d.log_cap) * 3;
     long long *e = d.log + (id * d.log_cap + (t + 1) % d.log_cap) * 3;
@@ -396,8 +401,11 @@ __global__ __launch_bounds__(kMsSub * kMsReal) void ms_reduce(const MsDev *__res
     e[1] = prev[1] + S2;
     e[2] = A;
     d.m0[id] = s1 / ((long long)d.L * d.L);
-    // every thread read t before the combine barrier
-    if (r == 0) d.t[g] = t + 1;
+    if (r == 0) {
+        __hip_atomic_store((gu64m *)(d.done + 16 * (size_t)g), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // every workgroup of the group read t before it was counted
+        d.t[g] = t + 1;
+    }
 }
 
 // Realization r of group g as int32 heights (grid-stride).
