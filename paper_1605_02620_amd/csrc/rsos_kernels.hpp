@@ -522,6 +522,26 @@ __device__ __forceinline__ int block_map(int wg, int n, int mode, int nbx)
     return wg;
 }
 
+// LDS row pitch of a byte-staged region.  Rounded up to a multiple of 64
+// bytes (half the 32 banks) it spreads the lanes of a wavefront over the
+// banks more evenly than the bare row length does, at the price of LDS per
+// block: done for the tile checkerboard where that price is at most 15%
+// (rows of 32 tiles at D = 8: 280 or 288 -> 320 bytes; measured faster),
+// not for narrower rows or the double-tiling schedule, whose latency-bound
+// phases need the blocks per CU more (measured slower).
+template <int ES, int RWL, int SCHED>
+struct RowPitch {
+    static constexpr int padded = (RWL + 63) & ~63;
+    static constexpr int v = (ES == 1 && SCHED == 0 && 100 * padded <= 115 * RWL) ? padded : RWL;
+};
+
+// LDS bytes of a block's narrow staging with its row pitch.
+template <int D, int TX, int TY, int CPC, int ES, int SCHED>
+struct NarrowBytes {
+    using G = BlockGeom<D, TX, TY, CPC>;
+    static constexpr int v = RowPitch<ES, G::RWL, SCHED>::v * G::RH * ES;
+};
+
 // Where a block's staging does not fit its narrow element type, the same
 // workgroup sweeps it again as SX x SY sub-blocks with the wide type EW.
 // The tile block shape never changes results (each sub-block recomputes the
@@ -571,9 +591,11 @@ template <> struct WideSize<void> { static constexpr int v = 0; };
 // path, and the compiler's own allocation is kept.  A workgroup of NT
 // threads puts NT / 256 waves on each SIMD, so the count is a multiple of
 // that; 256 bytes stand for the kernel's small static arrays.
-template <int D, int TX, int TY, int NT, int CPC, int ES, int EWS>
+template <int D, int TX, int TY, int NT, int CPC, int ES, int EWS, int SCHED = 0>
 struct WideOcc {
-    static constexpr int lds = WideSplit<D, TX, TY, NT, CPC, ES, EWS>::BYTES + 256;
+    static constexpr int W = WideSplit<D, TX, TY, NT, CPC, ES, EWS>::BYTES;
+    static constexpr int N = NarrowBytes<D, TX, TY, CPC, ES, SCHED>::v;
+    static constexpr int lds = (W > N ? W : N) + 256;
     static constexpr int per = NT >= 256 ? NT / 256 : 1;
     static constexpr int w0 = (163840 / lds) * (NT / 64) / 4;
     static constexpr int w = ((w0 > 7 ? 7 : w0) / per) * per;
@@ -599,6 +621,7 @@ template <int D, int TX, int TY, int NT, typename E, int SCHED, int U = 8>
 __device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by, long long t, int ox, int oy,
                                              int *s_bad, long long &ca, long long &cs2, bool commit_here, int b)
 {
+    constexpr int PP = RowPitch<(int)sizeof(E), BlockGeom<D, TX, TY, 4>::RWL, SCHED>::v;
     const uint32_t s = (uint32_t)t;
     using G = BlockGeom<D, TX, TY>;
     using Q = typename std::conditional<sizeof(E) <= 2, int, long long>::type;
@@ -634,7 +657,7 @@ __device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by,
         };
         auto stage = [&](int i, const int4 &v) {
             const int r = i / G::CH, cc = i - r * G::CH;
-            lds_put4<E>(lds + r * G::RWL + 4 * cc, v, ref);
+            lds_put4<E>(lds + r * PP + 4 * cc, v, ref);
             if (checked) {
                 vmin = min(vmin, min(min(v.x, v.y), min(v.z, v.w)));
                 vmax = max(vmax, max(max(v.x, v.y), max(v.z, v.w)));
@@ -673,7 +696,7 @@ __device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by,
     const int off = G::RING + cpad;  // LDS column of block column 0
     int acc = 0;
     Q q = 0;
-    sweep_phases<SCHED, D, TX, TY, NT, G::RWL, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    sweep_phases<SCHED, D, TX, TY, NT, PP, E, Q>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
     // a deposit on h raises S2 by 2h + 1; the staged value c stands for ref + c
     ca += acc;
     cs2 += 2ll * (long long)q + (long long)acc + 2ll * (long long)ref * acc;
@@ -708,7 +731,7 @@ __device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by,
             for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
-                const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
+                const E *src = lds + (G::RING + r) * PP + 4 * kslot;
                 store4_stream(hout + (size_t)gy * L + gc,
                               Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref));
             }
@@ -717,7 +740,7 @@ __device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by,
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
                 gint32 *row = hout + (size_t)gy * L;
-                const E *src = lds + (G::RING + r) * G::RWL + 4 * kslot;
+                const E *src = lds + (G::RING + r) * PP + 4 * kslot;
                 const int4 v = Lds4<E>::widen(*reinterpret_cast<const typename Lds4<E>::raw *>(src), ref);
                 if (!partial) {
                     store4(row + gc, v);
@@ -738,7 +761,7 @@ __device__ __forceinline__ bool region_sweep(E *lds, SurfDev &d, int bx, int by,
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
                 gint32 *row = hout + (size_t)gy * L;
-                const E *src = lds + (G::RING + r) * G::RWL + 4 * kt;
+                const E *src = lds + (G::RING + r) * PP + 4 * kt;
                 row[gct] = ref + (int)src[0];
                 if (m >= 2) row[gct + 1] = ref + (int)src[1];
                 if (m >= 3) row[gct + 2] = ref + (int)src[2];
@@ -773,11 +796,12 @@ __device__ __forceinline__ void wide_sweep(E *lds, SurfDev &d, int bx, int by, l
 // ---------------------------------------------------------------------------
 template <int D, int TX, int TY, int NT, typename E, typename EW, int SCHED = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    WideOcc<D, TX, TY, NT, 4, (int)sizeof(E), WideSize<EW>::v>::v))) void block_sweep(SurfDev *__restrict__ descs, int nsurf,
+    WideOcc<D, TX, TY, NT, 4, (int)sizeof(E), WideSize<EW>::v, SCHED>::v))) void block_sweep(SurfDev *__restrict__ descs, int nsurf,
                                                   const int *__restrict__ owner, int xmode, int xnbx)
 {
     using W = WideSplit<D, TX, TY, NT, 4, (int)sizeof(E), WideSize<EW>::v>;
-    __shared__ __attribute__((aligned(16))) uint8_t lds_raw[W::BYTES];
+    constexpr int NB = NarrowBytes<D, TX, TY, 4, (int)sizeof(E), SCHED>::v;
+    __shared__ __attribute__((aligned(16))) uint8_t lds_raw[NB > W::BYTES ? NB : W::BYTES];
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
 
@@ -886,6 +910,7 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
     const uint32_t s = (uint32_t)t;
     using G = BlockGeom<D, TX, TY, 8>;
     using S = Stage16<E>;
+    constexpr int PP = RowPitch<(int)sizeof(E), G::RWL, SCHED>::v;
     constexpr bool checked = sizeof(E) == 1;
     const int L = d.L, N = d.N, T = d.T;
     const uint32_t k0 = d.key0, k1 = d.key1;
@@ -922,7 +947,7 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
             w.y = pk_sub16(v.y, basep);
             w.z = pk_sub16(v.z, basep);
             w.w = pk_sub16(v.w, basep);
-            S::put(lds + r * G::RWL + 8 * cc, w, umax);
+            S::put(lds + r * PP + 8 * cc, w, umax);
         };
 #pragma unroll 1
         for (int g = 0; g < FULL; ++g) {
@@ -956,7 +981,7 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
     const int off = G::RING + cpad;
     int acc = 0;
     int q = 0;
-    sweep_phases<SCHED, D, TX, TY, NT, G::RWL, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    sweep_phases<SCHED, D, TX, TY, NT, PP, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
     {
         // true height of staged value 0: the reference site's height,
         // recovered from m0 of the sweep's start, less the staging bias
@@ -991,7 +1016,7 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
             for (int r = threadIdx.x / SPR; r < G::BH; r += RPP) {
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
-                const E *src = lds + (G::RING + r) * G::RWL + 8 * kslot;
+                const E *src = lds + (G::RING + r) * PP + 8 * kslot;
                 __builtin_nontemporal_store(S::get(*reinterpret_cast<const typename S::raw *>(src), basep),
                                             reinterpret_cast<gv4u *>(hout + (size_t)gy * L + gc));
             }
@@ -1000,7 +1025,7 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
                 gu16 *row = hout + (size_t)gy * L;
-                const E *src = lds + (G::RING + r) * G::RWL + 8 * kslot;
+                const E *src = lds + (G::RING + r) * PP + 8 * kslot;
                 if (!partial) {
                     *reinterpret_cast<gv4u *>(row + gc) = S::get(*reinterpret_cast<const typename S::raw *>(src), basep);
                 } else {
@@ -1019,7 +1044,7 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
                 int gy = gy0 + G::RING + r;
                 if (gy >= L) gy -= L;
                 gu16 *row = hout + (size_t)gy * L;
-                const E *src = lds + (G::RING + r) * G::RWL + 8 * kt;
+                const E *src = lds + (G::RING + r) * PP + 8 * kt;
 #pragma unroll
                 for (int k = 0; k < 7; ++k)
                     if (k < m) row[gct + k] = (uint16_t)(base_r + (uint32_t)(int)src[k]);
@@ -1047,11 +1072,12 @@ __device__ __forceinline__ void wide_sweep16(int16_t *lds, SurfDev &d, int bx, i
 // block_sweep on 16-bit residues: uint8 staging, int16 for the blocks that
 // do not fit it.
 template <int D, int TX, int TY, int NT, int SCHED = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WideOcc<D, TX, TY, NT, 8, 1, 2>::v))) void block_sweep16(SurfDev *__restrict__ descs, int nsurf,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WideOcc<D, TX, TY, NT, 8, 1, 2, SCHED>::v))) void block_sweep16(SurfDev *__restrict__ descs, int nsurf,
                                                     const int *__restrict__ owner, int xmode, int xnbx)
 {
     using W = WideSplit<D, TX, TY, NT, 8, 1, 2>;
-    __shared__ __attribute__((aligned(16))) uint8_t lds_raw[W::BYTES];
+    constexpr int NB = NarrowBytes<D, TX, TY, 8, 1, SCHED>::v;
+    __shared__ __attribute__((aligned(16))) uint8_t lds_raw[NB > W::BYTES ? NB : W::BYTES];
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
 

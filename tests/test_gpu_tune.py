@@ -107,7 +107,11 @@ def test_tuned_single_surface(rsos, oracle):
     t = surface.tune(L, N, D)
     _say(f"tuned L={L}: {t}")
     assert t["measured"] == 1 and t["candidates"] >= 2 and t["ms_per_sweep"] > 0
-    assert t["ms_per_sweep"] <= t["ms_first_fit"] * 1.0001
+    # the fastest candidate is never slower than the first fit; on a tie
+    # within 1% the tuner takes the column-strip XCD order of the fastest
+    # shape, which may then be up to 1% slower than the first fit
+    slack = 1.01 if t["xmode"] == 2 else 1.0
+    assert t["ms_per_sweep"] <= t["ms_first_fit"] * slack * 1.0001
     s = rsos.Surface(L, N=N, seed=seed, D=D, tune=True)
     s.sweep(n)
     r_h, r_log = _oracle(oracle, workloads.flat(L), L, N, D, seed, n)
