@@ -1093,8 +1093,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WideOcc<D, T
     const int bx = b % d.nbx, by = b / d.nbx;
     long long ca = 0, cs2 = 0;
     __syncthreads();  // s_bad cleared
-    if (__builtin_expect(!region_sweep16<D, TX, TY, NT, uint8_t, SCHED>(lds_raw, d, bx, by, t, ox, oy, &s_bad, ca,
-                                                                         cs2, true, b), 0))
+    // twelve 16-byte loads in flight per thread (the 32 x 8 region of 16-bit
+    // residues in one round of 256 threads; measured 1% faster than eight,
+    // within the same registers)
+    constexpr int U16 = SCHED == 0 ? 12 : 8;
+    if (__builtin_expect(!region_sweep16<D, TX, TY, NT, uint8_t, SCHED, U16>(lds_raw, d, bx, by, t, ox, oy, &s_bad, ca,
+                                                                              cs2, true, b), 0))
         wide_sweep16<D, TX / W::SX, TY / W::SY, NT, SCHED, W::SX, W::SY>((int16_t *)lds_raw, d, bx, by, t, ox, oy,
                                                                      &s_bad, ca, cs2, b);
 }
