@@ -125,8 +125,9 @@ def _traffic(kname, packed, schedule="checkerboard"):
 def bench_single(L, N, D, seed, steps, warmup, packed=False, schedule="checkerboard", tune=True):
     """K sweeps of one surface in one rsos_sweep call (hipGraph replays of
     one kernel per sweep), then the same again with every tile-block kernel
-    bracketed by HIP events on the surface's stream (graph replay off) for
-    the dominant kernel's mean duration.  tune: the launch configuration
+    timed by HIP events on the surface's stream that the runtime records at
+    the kernel's start and end (graph replay off) for the dominant kernel's
+    mean duration.  tune: the launch configuration
     comes from the autotuner (tuned when the surface is created)."""
     import torch
     import paper_1605_02620_amd as rsos

@@ -197,9 +197,10 @@ rsos_status rsos_moments(rsos_surface *s, rsos_moments_t *out);
  * (NULL with RSOS_FLAG_PACKED16). */
 rsos_status rsos_time(rsos_surface *s, int64_t *t, int32_t **d_current);
 
-/* Kernel timing.  While enabled, every tile-block sweep kernel launch of
- * the surface is bracketed by HIP events on the surface's stream (sweeps
- * are then issued one by one, not as hipGraph replays).  rsos_timing_read
+/* Kernel timing.  While enabled, every sweep's tile-block kernels are
+ * launched with HIP events on the surface's stream that the runtime records
+ * when the first kernel starts and the last one ends (hipExtLaunchKernel;
+ * sweeps are then issued one by one, not as hipGraph replays).  rsos_timing_read
  * synchronises and returns the number of timed launches and their mean and
  * total duration in milliseconds; it also clears the record. */
 rsos_status rsos_timing(rsos_surface *s, int enable);

@@ -12,6 +12,7 @@
 #include "rsos_ms.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdarg>
@@ -52,21 +53,33 @@ constexpr int kPsGrid = 2048;       // workgroups of the power-sum reduction
 // Block-kernel variants.  The tile block shape never changes results; it
 // only has to tile the lattice: T % TX == 0, T % TY == 0, region <= L.
 // ---------------------------------------------------------------------------
-typedef void (*BlockLaunch)(dim3, hipStream_t, SurfDev *, int, const int *, int, int);
+// e0 / e1: events recorded by the runtime when the kernel starts / ends
+// (hipExtLaunchKernel), for the timing mode; nullptr otherwise.
+typedef void (*BlockLaunch)(dim3, hipStream_t, SurfDev *, int, const int *, int, int, hipEvent_t, hipEvent_t);
 
 // E: LDS element type; EW: wider type for the blocks whose range does not
 // fit E (void: E always fits); SCHED 1: the double-tiling schedule
 template <int D, int TX, int TY, int NT, typename E, typename EW, int SCHED>
-void launch_block(dim3 grid, hipStream_t st, SurfDev *d, int n, const int *owner, int xmode, int xnbx)
+void launch_block(dim3 grid, hipStream_t st, SurfDev *d, int n, const int *owner, int xmode, int xnbx, hipEvent_t e0,
+                  hipEvent_t e1)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, EW, SCHED>), grid, dim3(NT), 0, st, d, n, owner,
-                       xmode, xnbx);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, EW, SCHED>), grid, dim3(NT), 0, st, e0, e1, 0, d,
+                              n, owner, xmode, xnbx);
+    else
+        hipLaunchKernelGGL((rsosk::block_sweep<D, TX, TY, NT, E, EW, SCHED>), grid, dim3(NT), 0, st, d, n, owner,
+                           xmode, xnbx);
 }
 
 template <int D, int TX, int TY, int NT>
-void launch_block16(dim3 grid, hipStream_t st, SurfDev *d, int n, const int *owner, int xmode, int xnbx)
+void launch_block16(dim3 grid, hipStream_t st, SurfDev *d, int n, const int *owner, int xmode, int xnbx, hipEvent_t e0,
+                    hipEvent_t e1)
 {
-    hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT>), grid, dim3(NT), 0, st, d, n, owner, xmode, xnbx);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT>), grid, dim3(NT), 0, st, e0, e1, 0, d, n, owner,
+                              xmode, xnbx);
+    else
+        hipLaunchKernelGGL((rsosk::block_sweep16<D, TX, TY, NT>), grid, dim3(NT), 0, st, d, n, owner, xmode, xnbx);
 }
 
 // The double-tiling schedule is built for the domain sizes the paper
@@ -489,13 +502,15 @@ struct SurfaceGroup {
 
     // the tile-block sweep proper: one workgroup per block, the whole sweep
     // in one launch per kernel instance
-    void launch_block_sweep()
+    void launch_block_sweep(hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
     {
-        for (const Shape &sh : shapes) {
+        for (size_t i = 0; i < shapes.size(); ++i) {
+            const Shape &sh = shapes[i];
             const Variant *v = sh.variant;
             BlockLaunch k = packed ? v->launch16 : sched == 1 ? v->launch_dt : v->launch;
             const int nbx = sh.count == 1 ? host[rows[sh.first]].nbx : 0;
-            k(dim3(sh.total_blocks), stream, d_desc + sh.first, sh.count, sh.d_owner, sh.xmode, nbx);
+            k(dim3(sh.total_blocks), stream, d_desc + sh.first, sh.count, sh.d_owner, sh.xmode, nbx,
+              i == 0 ? e0 : nullptr, i + 1 == shapes.size() ? e1 : nullptr);
         }
     }
 
@@ -503,14 +518,14 @@ struct SurfaceGroup {
     {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timing) {
+            // recorded by the runtime at the start of the sweep's first
+            // kernel and the end of its last
             HIP_TRY(hipEventCreate(&e0));
             HIP_TRY(hipEventCreate(&e1));
             timed.push_back({e0, e1});
-            HIP_TRY(hipEventRecord(e0, stream));
         }
-        launch_block_sweep();
+        launch_block_sweep(e0, e1);
         HIP_TRY(hipGetLastError());
-        if (timing) HIP_TRY(hipEventRecord(e1, stream));
         return RSOS_OK;
     }
 
@@ -1214,7 +1229,7 @@ extern "C" rsos_status rsos_sweep_static(const rsos_params *p, int32_t *d_h, int
         HIP_TRY(hipGetLastError());
     } else {
         BlockLaunch k = sched == 1 ? v->launch_dt : v->launch;
-        for (long long i = 0; i < n_mcs; ++i) k(dim3(d.nblocks), s, dd, 1, nullptr, 1, d.nbx);
+        for (long long i = 0; i < n_mcs; ++i) k(dim3(d.nblocks), s, dd, 1, nullptr, 1, d.nbx, nullptr, nullptr);
         HIP_TRY(hipGetLastError());
     }
     const unsigned grid = (unsigned)std::min<long long>((3 * n_mcs + 255) / 256, 64);

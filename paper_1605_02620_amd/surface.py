@@ -130,7 +130,8 @@ class Surface:
         return buf.value.decode()
 
     def timing(self, enable: bool = True):
-        """Brackets every tile-block kernel launch with HIP events."""
+        """Times every sweep's tile-block kernels with HIP events recorded
+        at their start and end (rsos_timing)."""
         check(lib().rsos_timing(self._h, int(bool(enable))))
 
     def timing_read(self):

@@ -117,6 +117,27 @@ def test_graph_replay_and_split_calls(rsos, oracle):
     _compare(a.log(1, n), r_log, a.heights(), r_h, L)
 
 
+def test_timing_mode(rsos, oracle):
+    """The timing mode (each sweep's kernels bracketed by events the runtime
+    records at their start and end) reports one duration per sweep and
+    changes no bit of the result; packed storage and a batch as well."""
+    import torch
+    L, N, D, seed, n = 512, 1, 8, 31, 12
+    _say(f"timing mode L={L} sweeps={n}")
+    for packed in (False, True):
+        st = torch.cuda.Stream()
+        a = rsos.Surface(L, N=N, seed=seed, D=D, stream=st, packed=packed)
+        a.sweep(4)
+        a.timing(True)
+        a.sweep(n - 4)
+        launches, mean_ms, total_ms = a.timing_read()
+        a.timing(False)
+        assert launches == n - 4 and 0 < mean_ms and abs(total_ms - mean_ms * launches) < 1e-6 * total_ms + 1e-9
+        r_h, r_log = _oracle_run(oracle, workloads.flat(L), L, N, D, seed, 0, n)
+        _compare(a.log(1, n), r_log, a.heights(), r_h, L)
+        a.close()
+
+
 def test_resume_from_checkpoint(rsos, oracle):
     L, N, D, seed = 256, 2, 8, 202
     _say("resume from t0=37")
