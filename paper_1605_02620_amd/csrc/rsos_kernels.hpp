@@ -138,8 +138,9 @@ struct TileBits {
 };
 
 // Geometry of a TX x TY tile block with its ring of D+1 sites, as staged in
-// LDS: region rows of RW sites stored with pitch RWL elements, shifted right
-// by the alignment pad (0..CPC-1) of the region's first column so that every
+// LDS: region rows of RW sites in RWL elements (CH chunks; the rows are laid
+// RWL elements apart, or RowPitch below for byte staging), shifted right by
+// the alignment pad (0..CPC-1) of the region's first column so that every
 // global load is an aligned 16-byte chunk of CPC cells (4 int32 or 8 uint16).
 template <int D, int TX, int TY, int CPC = 4>
 struct BlockGeom {
@@ -583,8 +584,9 @@ struct WideSplit {
 template <typename EW> struct WideSize { static constexpr int v = sizeof(EW); };
 template <> struct WideSize<void> { static constexpr int v = 0; };
 
-// Waves per SIMD that the LDS of a kernel with a wide path allows (160 KB
-// per CU, 4 SIMDs, at most 7).  For D = 8 the register budget is held to
+// Waves per SIMD that the LDS of a kernel with a wide path allows (the
+// larger of its narrow staging, with its row pitch, and its wide sub-blocks;
+// 160 KB per CU, 4 SIMDs, at most 7).  For D = 8 the register budget is held to
 // it, so that the rarely taken wide path (whose registers the compiler then
 // spills, in that path only) does not lower the occupancy of the main one;
 // for the other domain sizes the budget would force spills into the main
