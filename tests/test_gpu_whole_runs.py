@@ -91,9 +91,19 @@ def test_step_heights_whole_run(rsos, N):
     _single(rsos, f"step_L8192_N{N}")
 
 
-def test_ensemble_whole_run(rsos):
-    """The whole 256-surface ensemble in one batch for 10^4 sweeps; the
-    first surface of each size is compared sweep by sweep."""
+@pytest.mark.parametrize("N", [1, 2])
+def test_step_heights_whole_run_16bit_storage(rsos, N):
+    """The same runs with 16-bit residue storage (exact while N L <= 32766,
+    so N = 4 at L = 8192 is outside it): the same expected values."""
+    _single(rsos, f"step_L8192_N{N}", packed=True)
+
+
+@pytest.mark.parametrize("packed,tune", [(False, False), (True, True)], ids=["int32", "16bit_tuned"])
+def test_ensemble_whole_run(rsos, packed, tune):
+    """The whole 256-surface ensemble in one batch for 10^4 sweeps (int32
+    storage with the first-fit launch choice; 16-bit storage with the
+    autotuner's per-class choices); the first surface of each size is
+    compared sweep by sweep."""
     import torch
     ens = workloads.cfg_ensemble()
     names = {}
@@ -102,8 +112,9 @@ def test_ensemble_whole_run(rsos):
             names[s.L] = i
     golds = {L: _gold(f"ensemble_L{L}") for L in names}
     n = ens[0].sweeps
-    _say(f"ensemble: {len(ens)} surfaces, {n} sweeps")
-    b = rsos.Batch([(s.L, s.N, s.seed) for s in ens], D=8, log_cap=n + 1, stream=torch.cuda.Stream())
+    _say(f"ensemble: {len(ens)} surfaces, {n} sweeps, packed={packed}, tune={tune}")
+    b = rsos.Batch([(s.L, s.N, s.seed) for s in ens], D=8, log_cap=n + 1, stream=torch.cuda.Stream(),
+                   packed=packed, tune=tune)
     b.sweep(n)
     for L, i in names.items():
         meta, z = golds[L]
