@@ -20,6 +20,13 @@ Runs (names say what they are):
   served_subset      the served stream's jobs (2000 jobs, seed 5) with
                L^2 t_max <= 2^29, plus a seeded sample of 8 of the jobs with
                2^29 < L^2 t_max <= 2^33; each job alone
+  dt_L2048_D8, dt_L1024_D16  the double-tiling schedule (Sec. II's four
+               sets of sub-tiles), N = 1, seed 7, 1000 sweeps
+  ms_L256_N1, ms_L64_N10  the multisurface lock-step schedule, one group of
+               128 realizations (key = seed), seed 3, 1000 and 2000 sweeps;
+               stored: the whole log of realizations 0-3, every realization
+               at every 100th sweep, and SHA-256s of the whole [128, n] log
+               and of all final heights
 
 Usage: python tests/golden/make_whole_runs.py [names...] [--threads 7]
 Long runs checkpoint their state every 100 sweeps under --ckpt (default
@@ -77,6 +84,10 @@ def surfaces():
     return runs
 
 
+DT_RUNS = {"dt_L2048_D8": (2048, 1, 8, 7, 1000), "dt_L1024_D16": (1024, 1, 16, 7, 1000)}
+MS_RUNS = {"ms_L256_N1": (256, 1, 8, 3, 1000), "ms_L64_N10": (64, 10, 8, 3, 2000)}
+
+
 def served_subset():
     """The served stream's jobs that the oracle runs whole: every job with
     L^2 t_max <= 2^29 and a seeded sample of larger ones."""
@@ -89,7 +100,7 @@ def served_subset():
     return small + [mid[i] for i in pick]
 
 
-def run_surface(name, L, N, D, seed, n, threads, ckpt):
+def run_surface(name, L, N, D, seed, n, threads, ckpt, schedule="checkerboard"):
     os.makedirs(ckpt, exist_ok=True)
     ck = os.path.join(ckpt, name + ".npz")
     ref.set_threads(threads)
@@ -106,7 +117,8 @@ def run_surface(name, L, N, D, seed, n, threads, ckpt):
     step = 100
     while done < n:
         k = min(step, n - done)
-        logs.append(ref.run(h, L, N, D, seed=seed, t0=done, n=k))
+        sweep = ref.run_dt if schedule == "double" else ref.run
+        logs.append(sweep(h, L, N, D, seed=seed, t0=done, n=k))
         done += k
         np.savez(ck + ".tmp.npz", h=h, log=np.concatenate(logs), done=done)
         os.replace(ck + ".tmp.npz", ck)
@@ -116,7 +128,7 @@ def run_surface(name, L, N, D, seed, n, threads, ckpt):
     assert np.array_equal(lg[:, 0], np.arange(1, n + 1))
     s1, s2, a = (np.ascontiguousarray(lg[:, k]) for k in (1, 2, 3))
     np.savez_compressed(os.path.join(OUT, name + ".npz"), s1=s1, s2=s2, a=a)
-    meta = {"name": name, "L": L, "N": N, "D": D, "seed": seed, "sweeps": n,
+    meta = {"name": name, "L": L, "N": N, "D": D, "seed": seed, "sweeps": n, "schedule": schedule,
             "final_heights_sha256": sha_heights(h), "log_sha256": sha_arrays(s1, s2, a),
             "final": {"s1": int(s1[-1]), "s2": int(s2[-1]), "a": int(a[-1])},
             "oracle_threads": threads, "oracle_wall_s": round(time.perf_counter() - t0, 1)}
@@ -124,6 +136,27 @@ def run_surface(name, L, N, D, seed, n, threads, ckpt):
         json.dump(meta, f, indent=1)
     os.remove(ck)
     print(f"[{name}] written", flush=True)
+
+
+def run_ms(name, L, N, D, seed, n, threads):
+    ref.set_threads(threads)
+    h = np.zeros((128, L * L), dtype=np.int32)
+    t0 = time.perf_counter()
+    lg = ref.run_ms(h, L, N, D, seed=seed, t0=0, n=n)
+    assert np.array_equal(lg[0, :, 0], np.arange(1, n + 1))
+    s1, s2, a = (np.ascontiguousarray(lg[:, :, k]) for k in (1, 2, 3))
+    every = np.arange(99, n, 100)
+    np.savez_compressed(os.path.join(OUT, name + ".npz"),
+                        s1=s1[:4], s2=s2[:4], a=a[:4], every=every,
+                        s1_every=np.ascontiguousarray(s1[:, every]),
+                        s2_every=np.ascontiguousarray(s2[:, every]),
+                        a_every=np.ascontiguousarray(a[:, every]))
+    meta = {"name": name, "L": L, "N": N, "D": D, "seed": seed, "sweeps": n, "realizations": 128,
+            "final_heights_sha256": sha_heights(h), "log_sha256": sha_arrays(s1, s2, a),
+            "oracle_threads": threads, "oracle_wall_s": round(time.perf_counter() - t0, 1)}
+    with open(os.path.join(OUT, name + ".json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(f"[{name}] written ({meta['oracle_wall_s']} s)", flush=True)
 
 
 def _one_job(j):
@@ -177,6 +210,12 @@ def main():
     for nm in names:
         if nm == "served_subset":
             run_served(args.threads)
+        elif nm in DT_RUNS:
+            L, N, D, seed, n = DT_RUNS[nm]
+            run_surface(nm, L, N, D, seed, n, args.threads, args.ckpt, schedule="double")
+        elif nm in MS_RUNS:
+            L, N, D, seed, n = MS_RUNS[nm]
+            run_ms(nm, L, N, D, seed, n, args.threads)
         else:
             L, N, D, seed, n = runs[nm]
             run_surface(nm, L, N, D, seed, n, args.threads, args.ckpt)

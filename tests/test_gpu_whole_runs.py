@@ -10,6 +10,12 @@ the benchmark runs them (non-default stream, hipGraph replays).
                      ensemble, 10^4 sweeps, run inside the whole ensemble
   served_subset      the served stream's jobs with L^2 t_max <= 2^29 plus a
                      seeded sample of larger ones, served together
+  dt_L*_D*           the double-tiling schedule (Sec. II), 1000 sweeps,
+                     L = 2048 with D = 8 and L = 1024 with D = 16
+  ms_L*_N*           the multisurface lock-step mode, one group of 128
+                     realizations: L = 256, N = 1 for 1000 sweeps (the
+                     byte-staged kernel) and L = 64, N = 10 for 2000 sweeps
+                     (the 16-bit-staged one)
 
 A run whose expected values have not been generated yet is skipped with
 that reason.
@@ -65,11 +71,12 @@ def _single(rsos, name, packed=False):
     import torch
     meta, z = _gold(name)
     L, N, D, seed, n = meta["L"], meta["N"], meta["D"], meta["seed"], meta["sweeps"]
-    _say(f"{name}: L={L} N={N} D={D} seed={seed} sweeps={n} packed={packed}")
+    sched = meta.get("schedule", "checkerboard")
+    _say(f"{name}: L={L} N={N} D={D} seed={seed} sweeps={n} packed={packed} schedule={sched}")
     s = rsos.Surface(L, N=N, seed=seed, D=D, log_cap=n + 1, stream=torch.cuda.Stream(), packed=packed,
-                     tune=True)
+                     schedule=sched, tune=True)
     from paper_1605_02620_amd import surface
-    c = surface.tune(L, N, D, packed=packed)
+    c = surface.tune(L, N, D, packed=packed, schedule=sched)
     _say(f"{name}: {c['TX']}x{c['TY']} tiles, {c['NT']} threads, xmode {c['xmode']}, graphs of {c['graph_sweeps']}")
     s.sweep(n)
     lg = s.log(1, n)
@@ -153,3 +160,40 @@ def test_served_subset_whole_runs(rsos):
         assert _sha(h) == meta["final_heights_sha256"][str(jid)], f"job {jid}: final heights differ"
         eng.release(handle[jid])
     eng.close()
+
+
+@pytest.mark.parametrize("name", ["dt_L2048_D8", "dt_L1024_D16"])
+def test_double_tiling_whole_run(rsos, name):
+    """The double-tiling schedule run whole (the autotuner's choice; this
+    schedule runs with int32 storage only)."""
+    _single(rsos, name)
+
+
+@pytest.mark.parametrize("name", ["ms_L256_N1", "ms_L64_N10"])
+def test_multisurface_whole_run(rsos, name):
+    """One group of 128 lock-step realizations run whole: the SHA-256 of
+    every realization's whole (S1, S2, A) log and of all final heights; the
+    stored samples (every realization at every 100th sweep, the whole log
+    of realizations 0-3) say where a difference starts."""
+    import torch
+    meta, z = _gold(name)
+    L, N, seed, n = meta["L"], meta["N"], meta["seed"], meta["sweeps"]
+    assert meta["D"] == 8 and meta["realizations"] == 128
+    _say(f"{name}: L={L} N={N} seed={seed} sweeps={n}, 128 realizations")
+    m = rsos.MultiSurface(L, N=N, seed=seed, groups=1, log_cap=n + 1, stream=torch.cuda.Stream())
+    m.sweep(n)
+    logs = [m.log(r, 1, n) for r in range(128)]
+    for r in range(4):
+        _check_log(logs[r], {k: z[k][r] for k in ("s1", "s2", "a")}, f"{name} realization {r}")
+    ev = z["every"]
+    for name_, key in (("s1", "s1_every"), ("s2", "s2_every"), ("accepted", "a_every")):
+        got = np.stack([lg[name_][ev] for lg in logs])
+        bad = np.argwhere(got != z[key])
+        assert bad.size == 0, f"{name}: {name_} differs at realization {bad[0][0]}, t={int(ev[bad[0][1]]) + 1}"
+    m_ = hashlib.sha256()
+    for name_ in ("s1", "s2", "accepted"):
+        m_.update(np.ascontiguousarray(np.stack([lg[name_] for lg in logs]), dtype="<i8").tobytes())
+    assert m_.hexdigest() == meta["log_sha256"], f"{name}: whole logs differ"
+    hs = np.stack([m.heights(r) for r in range(128)])
+    assert _sha(hs) == meta["final_heights_sha256"], f"{name}: final heights differ"
+    m.close()
