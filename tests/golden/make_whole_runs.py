@@ -22,8 +22,9 @@ Runs (names say what they are):
                2^29 < L^2 t_max <= 2^33; each job alone
   dt_L2048_D8, dt_L1024_D16  the double-tiling schedule (Sec. II's four
                sets of sub-tiles), N = 1, seed 7, 1000 sweeps
-  ms_L256_N1, ms_L64_N10  the multisurface lock-step schedule, one group of
-               128 realizations (key = seed), seed 3, 1000 and 2000 sweeps;
+  ms_L256_N1, ms_L64_N8, ms_L64_N10  the multisurface lock-step schedule,
+               one group of 128 realizations (key = seed), seed 3, 1000,
+               2000 and 2000 sweeps;
                stored: the whole log of realizations 0-3, every realization
                at every 100th sweep, and SHA-256s of the whole [128, n] log
                and of all final heights
@@ -85,7 +86,8 @@ def surfaces():
 
 
 DT_RUNS = {"dt_L2048_D8": (2048, 1, 8, 7, 1000), "dt_L1024_D16": (1024, 1, 16, 7, 1000)}
-MS_RUNS = {"ms_L256_N1": (256, 1, 8, 3, 1000), "ms_L64_N10": (64, 10, 8, 3, 2000)}
+MS_RUNS = {"ms_L256_N1": (256, 1, 8, 3, 1000), "ms_L64_N8": (64, 8, 8, 3, 2000),
+           "ms_L64_N10": (64, 10, 8, 3, 2000)}
 
 
 def served_subset():

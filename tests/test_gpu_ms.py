@@ -38,7 +38,8 @@ def _oracle_group(oracle, L, N, seed, n):
 # 16-bit-staged one
 @pytest.mark.parametrize("L,N,groups,sweeps", [(16, 1, 1, 50), (64, 1, 2, 40), (128, 2, 1, 20),
                                                (256, 1, 2, 10), (256, 4, 1, 8), (512, 1, 1, 70),
-                                               (64, 9, 1, 60), (64, 10, 1, 60), (32, 40, 2, 80)])
+                                               (64, 8, 1, 60), (64, 9, 1, 60), (64, 10, 1, 60),
+                                               (32, 40, 2, 80)])
 def test_ms_matches_oracle(rsos, oracle, L, N, groups, sweeps):
     _say(f"L={L} N={N} groups={groups} sweeps={sweeps}")
     seed = 1000 + L + N

@@ -13,9 +13,9 @@ the benchmark runs them (non-default stream, hipGraph replays).
   dt_L*_D*           the double-tiling schedule (Sec. II), 1000 sweeps,
                      L = 2048 with D = 8 and L = 1024 with D = 16
   ms_L*_N*           the multisurface lock-step mode, one group of 128
-                     realizations: L = 256, N = 1 for 1000 sweeps (the
-                     byte-staged kernel) and L = 64, N = 10 for 2000 sweeps
-                     (the 16-bit-staged one)
+                     realizations: L = 256, N = 1 for 1000 sweeps and
+                     L = 64, N = 8 for 2000 sweeps (the byte-staged kernel),
+                     L = 64, N = 10 for 2000 sweeps (the 16-bit-staged one)
 
 A run whose expected values have not been generated yet is skipped with
 that reason.
@@ -169,7 +169,7 @@ def test_double_tiling_whole_run(rsos, name):
     _single(rsos, name)
 
 
-@pytest.mark.parametrize("name", ["ms_L256_N1", "ms_L64_N10"])
+@pytest.mark.parametrize("name", ["ms_L256_N1", "ms_L64_N8", "ms_L64_N10"])
 def test_multisurface_whole_run(rsos, name):
     """One group of 128 lock-step realizations run whole: the SHA-256 of
     every realization's whole (S1, S2, A) log and of all final heights; the
