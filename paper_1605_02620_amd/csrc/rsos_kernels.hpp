@@ -157,8 +157,9 @@ struct BlockGeom {
 // One attempt on the site at field f of a tile whose site (u, v) sits at LDS
 // index base + v*P + u (neighbours at +-1 and +-P).  E is the LDS element
 // type: narrow types hold heights relative to a per-block base, int32 raw
-// heights.  Adds the acceptance to acc and, when accepted, the staged value
-// c before the deposit to q (a deposit on height h raises sum h^2 by 2h + 1).
+// heights.  Adds the acceptance to acc (minus the acceptance with unsigned
+// byte staging) and, when accepted, the staged value c before the deposit
+// to q (a deposit on height h raises sum h^2 by 2h + 1).
 template <int D, int P, typename E, typename Q>
 __device__ __forceinline__ void attempt(E *lds, int base, uint32_t f, int N, int &acc, Q &q)
 {
@@ -174,13 +175,27 @@ __device__ __forceinline__ void attempt(E *lds, int base, uint32_t f, int N, int
         const int i1 = (base - 1) + (int)__umul24(f >> LOG2D, (uint32_t)P) + (int)(f & (D - 1));
         const uint32_t *w = reinterpret_cast<const uint32_t *>(lds + (i1 & ~3));
         const uint32_t t3 = __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)i1);
-        const int l = (int)(t3 & 0xFFu), r = (int)((t3 >> 16) & 0xFFu);
+        // min(left, right) straight from bytes 0 and 2 of t3 (one instruction
+        // where the compiler would extract both bytes first)
+        uint32_t lr;
+        asm("v_min_u16_sdwa %0, %1, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_2"
+            : "=v"(lr) : "v"(t3));
         c = (int)((t3 >> 8) & 0xFFu);
-        m = min(min(l, r), min((int)lds[i1 + 1 - P], (int)lds[i1 + 1 + P]));
-        const int ok = (int)((uint32_t)(c - m - N) >> 31);
-        q += __mul24(c, ok);
-        lds[i1 + 1] = (E)(c + ok);
-        acc += ok;
+        m = (int)min(min(lr, (uint32_t)lds[i1 + 1 - P]), (uint32_t)lds[i1 + 1 + P]);
+        // all ones if accepted, else zero
+        const int nok = (c - m - N) >> 31;
+        // c & nok and c - nok with c taken as byte 1 of t3 by the
+        // instructions themselves
+        int qc, cn;
+        asm("v_and_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+            : "=v"(qc) : "v"(nok), "v"(t3));
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:DWORD"
+            : "=v"(cn) : "v"(t3), "v"(nok));
+        q += qc;
+        lds[i1 + 1] = (E)cn;
+        // this staging counts acceptances negatively (one instruction less
+        // per attempt); region_sweep16 negates the block's count
+        acc += nok;
         return;
     } else {
         c = lds[idx];
@@ -984,6 +999,8 @@ __device__ __forceinline__ bool region_sweep16(E *lds, SurfDev &d, int bx, int b
     int acc = 0;
     int q = 0;
     sweep_phases<SCHED, D, TX, TY, NT, PP, E, int>(lds, off, bx, by, T, s, N, k0, k1, acc, q);
+    // the unsigned byte staging counts acceptances negatively
+    if constexpr (std::is_same<E, uint8_t>::value) acc = -acc;
     {
         // true height of staged value 0: the reference site's height,
         // recovered from m0 of the sweep's start, less the staging bias
